@@ -1,0 +1,189 @@
+/*
+ * rfchan.h -- C ABI of the MI355X (gfx950) readout channelizer and demodulator.
+ *
+ * Implements the GPU signal-processing hot path of Minutolo et al., "A flexible
+ * GPU-accelerated radio-frequency readout for superconducting detectors"
+ * (arXiv:1812.02200): a critically sampled polyphase filter bank (Sec. III.A)
+ * and a bank of direct demodulators (Sec. III.B), on a continuous stream of
+ * complex-baseband int16 I/Q samples (the 14-bit, 200 Ms/s ADC stream of
+ * Sec. II.A).  Filter history and oscillator phase stay on the device between
+ * calls, so a stream may be cut into buffers of any size.
+ *
+ * Conventions shared by every call:
+ *  - Samples are interleaved int16 I/Q in device memory: I[m] at index 2m,
+ *    Q[m] at 2m+1, x[m] = I[m] + j Q[m].  Pointers must be 4-byte aligned
+ *    (16-byte alignment gives the fastest loads).
+ *  - Outputs are complex64: float pairs (re, im), interleaved.
+ *  - Work is asynchronous on the HIP stream passed as `hip_stream`
+ *    (a hipStream_t; NULL means the default stream).  Successive calls on one
+ *    handle are ordered even if they name different streams.  The caller owns
+ *    every buffer it passes and keeps it alive until the stream has reached
+ *    the work.
+ *  - Every call returns a status (RF_OK = 0).  A call that fails leaves the
+ *    handle's state unchanged.  Nothing throws across the ABI.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Device memory is allocated only by the *_create calls; *_process calls
+ *    never allocate.
+ */
+#ifndef RFCHAN_H
+#define RFCHAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define RF_OK 0
+#define RF_EINVAL 1        /* invalid argument (null pointer, bad size, ...) */
+#define RF_ENOMEM 2        /* device or host allocation failed */
+#define RF_EDEVICE 3       /* a HIP runtime call failed (see rf_last_error) */
+#define RF_ECAPACITY 4     /* output buffer too small for this call */
+#define RF_EAGAIN 5        /* resource busy / does not fit now; retry later */
+#define RF_EUNSUPPORTED 6  /* valid request this build does not support */
+
+/* Short description of a status code (static string). */
+const char *rf_strerror(int status);
+
+/* Detail of the most recent failure on the calling thread ("" if none). */
+const char *rf_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int rf_version(void);
+
+/* ============================================================ PFB channelizer
+ *
+ * Critically sampled polyphase filter bank (paper Sec. III.A): N channels,
+ * decimation N, a prototype FIR of length N*M (M taps per channel).  Frame p
+ * of the stream covers samples [p*N, p*N + N*M) and is
+ *     v_p[n] = sum_{m=0}^{M-1} h[m*N + n] * x[p*N + m*N + n],   n in [0, N)
+ *     X_p[k] = sum_{n=0}^{N-1} v_p[n] * exp(-2 pi i k n / N),   k in [0, N)
+ * (unnormalised forward DFT, bins in natural order: bin k >= N/2 is the
+ * negative frequency (k - N) fs / N).  Only frames whose N*M samples have all
+ * arrived are emitted, so the first frame appears once N*M samples exist.
+ */
+typedef struct rf_pfb *rf_pfb_t;
+
+/* DFT stage implementations. */
+#define RF_DFT_FFT_F32 0      /* FP32 FFT (radix-4/16 Stockham in LDS)        */
+#define RF_DFT_MFMA_F16X2 1   /* DFT as a GEMM on FP16 MFMA, hi/lo split, N<=256 */
+#define RF_DFT_MFMA_BF16X2 2  /* DFT as a GEMM on BF16 MFMA, hi/lo split, N<=256 */
+
+/* Create a channelizer on the current HIP device.
+ *   out       receives the handle.
+ *   nchan     N: a power of two, 16 <= N <= 4096.
+ *   ntaps     M: 1 <= M <= 16.
+ *   proto     host array of N*M FP32 prototype taps h[0..N*M); copied, the
+ *             caller may free it on return.
+ *   dft_mode  one of RF_DFT_*; the MFMA modes need N <= 256
+ *             (RF_EUNSUPPORTED otherwise).
+ *   max_samples_per_call  largest nsamples a single pfb_process will accept
+ *             (>= 1).  Bounds the work of one call; no memory scales with it.
+ * Allocates all device state (taps, twiddles, two history buffers of N*M
+ * samples).  Returns RF_EINVAL for bad sizes, RF_ENOMEM / RF_EDEVICE on
+ * allocation or copy failure. */
+int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto,
+               int32_t dft_mode, uint64_t max_samples_per_call);
+
+/* Number of frames the next pfb_process of `nsamples` samples will emit; a
+ * pure host-side function of the handle's sample count (no device sync). */
+uint64_t pfb_frames_for(rf_pfb_t pfb, uint64_t nsamples);
+
+/* Channelize the next `nsamples` samples of the stream.
+ *   iq_dev          device pointer, 2*nsamples int16 (may be NULL if nsamples == 0).
+ *   nsamples        any value from 0 to max_samples_per_call, including < N.
+ *   out_dev         device pointer to out_cap_frames * N complex64 values; frame
+ *                   f of this call is written at out_dev + 2*N*f (frame-major).
+ *   out_cap_frames  capacity in frames; RF_ECAPACITY if < pfb_frames_for().
+ *   frames_out      host pointer (may be NULL): number of frames written.
+ *   hip_stream      hipStream_t to enqueue on.
+ * Enqueues one kernel; returns without waiting for it. */
+int pfb_process(rf_pfb_t pfb, const int16_t *iq_dev, uint64_t nsamples, float *out_dev,
+                uint64_t out_cap_frames, uint64_t *frames_out, void *hip_stream);
+
+/* Counters of the stream so far (host-side, no sync). Any pointer may be NULL. */
+int pfb_counters(rf_pfb_t pfb, uint64_t *samples_in, uint64_t *frames_out,
+                 uint64_t *history_samples);
+
+/* Exact checkpoint of the stream state (history samples and counters).
+ * pfb_get_state: if blob is NULL or *size is too small, sets *size to the
+ * required size and returns RF_ECAPACITY (RF_OK when blob is NULL);
+ * otherwise waits for the handle's last stream and copies the state out.
+ * pfb_set_state: restores a blob from a handle with the same N and M
+ * (RF_EINVAL otherwise); waits for the handle's last stream first. */
+int pfb_get_state(rf_pfb_t pfb, void *blob, size_t *size);
+int pfb_set_state(rf_pfb_t pfb, const void *blob, size_t size);
+
+/* Forget the stream: empty history, counters to zero (waits for pending work). */
+int pfb_reset(rf_pfb_t pfb);
+
+/* Wait for pending work and free the handle (NULL is accepted). */
+int pfb_destroy(rf_pfb_t pfb);
+
+/* ============================================================ DDC bank
+ *
+ * Direct demodulation of a set of tones (paper Sec. III.B).  Tone t has a
+ * 64-bit integer phase accumulator: at absolute sample m its phase is
+ *     phi_t[m] = phase0[t] + m * phase_inc[t]   (mod 2^64),
+ * the oscillator value is c_t[m] = Tab[phi_t[m] >> 48] from a 2^16-entry FP32
+ * cos/sin table (truncation, no interpolation), and the output is
+ *     y_t[n] = sum_{k=0}^{T-1} h[k] * x[n*D + T-1-k] * conj(c_t[n*D + T-1-k])
+ * for every n with n*D + T - 1 < samples received: mix down, a T-tap FIR
+ * low-pass (the paper's moving average is h = 1/D, T = D) and decimation by D.
+ * Tab[i] = (cos, sin)(2 pi i / 2^16) rounded to FP32, defined through the
+ * quarter wave q[j] = fp32(sin(pi j / 2^15)), j = 0..2^14, by symmetry.
+ * A tone at frequency f of a stream sampled at fs has
+ * phase_inc = round(f / fs * 2^64) mod 2^64.
+ */
+typedef struct rf_ddc *rf_ddc_t;
+
+/* Create a demodulator bank on the current HIP device.
+ *   ntones     1 <= ntones <= 65536.
+ *   phase_inc  host array [ntones] of 64-bit tuning words (copied).
+ *   phase0     host array [ntones] of initial phases, or NULL for all zero.
+ *   ntaps      T: 1 <= T <= 4096.
+ *   lpf        host array [T] of FP32 low-pass taps h[0..T) (copied).
+ *   decim      D: 1 <= D <= 2^20.
+ *   max_samples_per_call  largest nsamples one ddc_process accepts (>= 1).
+ * Returns RF_EINVAL / RF_ENOMEM / RF_EDEVICE as pfb_create. */
+int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc,
+               const uint64_t *phase0, int32_t ntaps, const float *lpf, int32_t decim,
+               uint64_t max_samples_per_call);
+
+/* Outputs per tone that the next ddc_process of `nsamples` samples emits. */
+uint64_t ddc_outputs_for(rf_ddc_t ddc, uint64_t nsamples);
+
+/* Demodulate the next `nsamples` samples.
+ *   out_dev  device pointer; output n of tone t (n counted from this call's
+ *            first output) is written at out_dev + 2*(t*ld + n): tone-major.
+ *   ld       row stride in complex values, >= ddc_outputs_for(nsamples)
+ *            (RF_ECAPACITY otherwise).
+ *   nout     host pointer (may be NULL): outputs per tone written.
+ * Enqueues one kernel on hip_stream and returns. */
+int ddc_process(rf_ddc_t ddc, const int16_t *iq_dev, uint64_t nsamples, float *out_dev,
+                uint64_t ld, uint64_t *nout, void *hip_stream);
+
+/* Phase of every tone at the next unreceived sample, phase0 + S*phase_inc
+ * (mod 2^64), as computed on the device by the last ddc_process; waits for the
+ * handle's last stream.  phase_host: host array [ntones]. */
+int ddc_get_phase(rf_ddc_t ddc, uint64_t *phase_host);
+
+/* Counters (host-side, no sync). Any pointer may be NULL. */
+int ddc_counters(rf_ddc_t ddc, uint64_t *samples_in, uint64_t *outputs_out,
+                 uint64_t *history_samples);
+
+/* Checkpoint / restore / reset / free, with the semantics of the pfb_ calls.
+ * A state blob restores onto a bank with the same ntones, tuning words,
+ * phases, taps and decimation. */
+int ddc_get_state(rf_ddc_t ddc, void *blob, size_t *size);
+int ddc_set_state(rf_ddc_t ddc, const void *blob, size_t size);
+int ddc_reset(rf_ddc_t ddc);
+int ddc_destroy(rf_ddc_t ddc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFCHAN_H */

@@ -1,0 +1,9 @@
+"""MI355X-native readout channelizer and demodulator (arXiv:1812.02200 hot path).
+
+The computation lives in librfchan.so (hand-written HIP kernels for gfx950 behind
+the C ABI of include/rfchan.h); this package is its thin Python binding.
+"""
+from ._lib import (  # noqa: F401
+    RF_DFT_FFT_F32, RF_DFT_MFMA_BF16X2, RF_DFT_MFMA_F16X2, RF_EAGAIN, RF_ECAPACITY, RF_EDEVICE,
+    RF_EINVAL, RF_ENOMEM, RF_EUNSUPPORTED, RF_OK, LIB_PATH, Ddc, Pfb, RfError, lib, version,
+)

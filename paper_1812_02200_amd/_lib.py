@@ -1,0 +1,278 @@
+"""ctypes binding of librfchan.so (the C ABI declared in include/rfchan.h).
+
+Argument marshalling only: torch tensors supply device pointers and HIP stream
+handles, every step of the computation runs in the library's HIP kernels.
+There is no fallback: if the library is missing or a call fails, an exception
+is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librfchan.so")
+
+RF_OK = 0
+RF_EINVAL = 1
+RF_ENOMEM = 2
+RF_EDEVICE = 3
+RF_ECAPACITY = 4
+RF_EAGAIN = 5
+RF_EUNSUPPORTED = 6
+
+RF_DFT_FFT_F32 = 0
+RF_DFT_MFMA_F16X2 = 1
+RF_DFT_MFMA_BF16X2 = 2
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes); mirrors include/rfchan.h
+SIGNATURES = {
+    "rf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "rf_last_error": (ctypes.c_char_p, []),
+    "rf_version": (ctypes.c_int, []),
+    "pfb_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _I32, _P, _I32, _U64]),
+    "pfb_frames_for": (_U64, [_P, _U64]),
+    "pfb_process": (ctypes.c_int, [_P, _P, _U64, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "pfb_counters": (ctypes.c_int, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "pfb_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(_SZ)]),
+    "pfb_set_state": (ctypes.c_int, [_P, _P, _SZ]),
+    "pfb_reset": (ctypes.c_int, [_P]),
+    "pfb_destroy": (ctypes.c_int, [_P]),
+    "ddc_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32, _P, _I32, _U64]),
+    "ddc_outputs_for": (_U64, [_P, _U64]),
+    "ddc_process": (ctypes.c_int, [_P, _P, _U64, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "ddc_get_phase": (ctypes.c_int, [_P, _P]),
+    "ddc_counters": (ctypes.c_int, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "ddc_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(_SZ)]),
+    "ddc_set_state": (ctypes.c_int, [_P, _P, _SZ]),
+    "ddc_reset": (ctypes.c_int, [_P]),
+    "ddc_destroy": (ctypes.c_int, [_P]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class RfError(RuntimeError):
+    def __init__(self, status: int, call: str, detail: str):
+        super().__init__("%s failed: %s (%s)" % (call, detail or "", status_name(status)))
+        self.status = status
+
+
+def status_name(status: int) -> str:
+    return {0: "RF_OK", 1: "RF_EINVAL", 2: "RF_ENOMEM", 3: "RF_EDEVICE", 4: "RF_ECAPACITY",
+            5: "RF_EAGAIN", 6: "RF_EUNSUPPORTED"}.get(status, "status %d" % status)
+
+
+def lib():
+    """Load librfchan.so once (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "librfchan.so is not built (%s); run `python -m paper_1812_02200_amd.build`"
+                    % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+        return _lib
+
+
+def check(status: int, call: str) -> None:
+    if status != RF_OK:
+        detail = lib().rf_last_error().decode(errors="replace")
+        raise RfError(status, call, detail)
+
+
+def version() -> int:
+    return int(lib().rf_version())
+
+
+def _torch():
+    import torch  # noqa: WPS433 (device memory and streams only)
+    return torch
+
+
+def _stream_handle(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_iq(iq):
+    torch = _torch()
+    if not isinstance(iq, torch.Tensor) or iq.dtype != torch.int16 or not iq.is_cuda:
+        raise TypeError("iq must be an int16 CUDA/HIP tensor of interleaved I/Q")
+    if not iq.is_contiguous():
+        raise ValueError("iq must be contiguous")
+    if iq.numel() % 2:
+        raise ValueError("iq must hold an even number of int16 (I/Q pairs)")
+    return iq.numel() // 2
+
+
+class Pfb:
+    """Polyphase filter-bank channelizer handle (pfb_* calls)."""
+
+    def __init__(self, nchan: int, ntaps: int, proto, dft_mode: int = RF_DFT_FFT_F32,
+                 max_samples_per_call: int = 1 << 24):
+        import numpy as np
+        h = np.ascontiguousarray(np.asarray(proto, dtype=np.float32).reshape(-1))
+        if h.size != nchan * ntaps:
+            raise ValueError("prototype needs nchan*ntaps = %d taps" % (nchan * ntaps))
+        self.N, self.M = int(nchan), int(ntaps)
+        self._h = _P()
+        check(lib().pfb_create(ctypes.byref(self._h), self.N, self.M, h.ctypes.data, int(dft_mode),
+                               int(max_samples_per_call)), "pfb_create")
+        self.max_samples = int(max_samples_per_call)
+
+    def frames_for(self, nsamples: int) -> int:
+        return int(lib().pfb_frames_for(self._h, int(nsamples)))
+
+    def process(self, iq, out=None, stream=None):
+        """Channelize int16 I/Q tensor `iq`; returns a complex64 tensor [frames, N]."""
+        torch = _torch()
+        n = _check_iq(iq)
+        F = self.frames_for(n)
+        if out is None:
+            out = torch.empty((max(F, 1), self.N), dtype=torch.complex64, device=iq.device)
+        if out.dtype != torch.complex64 or not out.is_contiguous():
+            raise TypeError("out must be a contiguous complex64 tensor")
+        cap = out.numel() // self.N
+        got = _U64(0)
+        check(lib().pfb_process(self._h, iq.data_ptr() if n else None, n, out.data_ptr(), cap,
+                                ctypes.byref(got), _stream_handle(stream)), "pfb_process")
+        return out.view(-1, self.N)[: got.value]
+
+    def process_ptr(self, iq_ptr: int, nsamples: int, out_ptr: int, out_cap_frames: int,
+                    stream_handle: int) -> int:
+        got = _U64(0)
+        check(lib().pfb_process(self._h, iq_ptr, nsamples, out_ptr, out_cap_frames,
+                                ctypes.byref(got), stream_handle), "pfb_process")
+        return got.value
+
+    def counters(self):
+        a, b, c = _U64(), _U64(), _U64()
+        check(lib().pfb_counters(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "pfb_counters")
+        return a.value, b.value, c.value
+
+    def get_state(self) -> bytes:
+        sz = _SZ(0)
+        check(lib().pfb_get_state(self._h, None, ctypes.byref(sz)), "pfb_get_state")
+        buf = ctypes.create_string_buffer(sz.value)
+        check(lib().pfb_get_state(self._h, buf, ctypes.byref(sz)), "pfb_get_state")
+        return buf.raw[: sz.value]
+
+    def set_state(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().pfb_set_state(self._h, buf, len(blob)), "pfb_set_state")
+
+    def reset(self) -> None:
+        check(lib().pfb_reset(self._h), "pfb_reset")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            check(lib().pfb_destroy(h), "pfb_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ddc:
+    """Direct-demodulation bank handle (ddc_* calls)."""
+
+    def __init__(self, phase_inc, lpf, decim: int, phase0=None,
+                 max_samples_per_call: int = 1 << 24):
+        import numpy as np
+        inc = np.ascontiguousarray(np.asarray(phase_inc, dtype=np.uint64).reshape(-1))
+        p0 = None if phase0 is None else np.ascontiguousarray(
+            np.asarray(phase0, dtype=np.uint64).reshape(-1))
+        if p0 is not None and p0.size != inc.size:
+            raise ValueError("phase0 must have one entry per tone")
+        h = np.ascontiguousarray(np.asarray(lpf, dtype=np.float32).reshape(-1))
+        self.ntones, self.T, self.D = int(inc.size), int(h.size), int(decim)
+        self._h = _P()
+        check(lib().ddc_create(ctypes.byref(self._h), self.ntones, inc.ctypes.data,
+                               None if p0 is None else p0.ctypes.data, self.T, h.ctypes.data,
+                               self.D, int(max_samples_per_call)), "ddc_create")
+        self.max_samples = int(max_samples_per_call)
+
+    def outputs_for(self, nsamples: int) -> int:
+        return int(lib().ddc_outputs_for(self._h, int(nsamples)))
+
+    def process(self, iq, out=None, stream=None):
+        """Demodulate int16 I/Q tensor `iq`; returns complex64 [ntones, nout] (a view of out)."""
+        torch = _torch()
+        n = _check_iq(iq)
+        nout = self.outputs_for(n)
+        if out is None:
+            out = torch.empty((self.ntones, max(nout, 1)), dtype=torch.complex64, device=iq.device)
+        if out.dtype != torch.complex64 or out.dim() != 2 or out.shape[0] != self.ntones:
+            raise TypeError("out must be complex64 [ntones, ld]")
+        if out.stride(1) != 1:
+            raise ValueError("out rows must be contiguous")
+        ld = out.stride(0)
+        got = _U64(0)
+        check(lib().ddc_process(self._h, iq.data_ptr() if n else None, n, out.data_ptr(), ld,
+                                ctypes.byref(got), _stream_handle(stream)), "ddc_process")
+        return out[:, : got.value]
+
+    def process_ptr(self, iq_ptr: int, nsamples: int, out_ptr: int, ld: int,
+                    stream_handle: int) -> int:
+        got = _U64(0)
+        check(lib().ddc_process(self._h, iq_ptr, nsamples, out_ptr, ld, ctypes.byref(got),
+                                stream_handle), "ddc_process")
+        return got.value
+
+    def phase(self):
+        import numpy as np
+        out = np.empty(self.ntones, dtype=np.uint64)
+        check(lib().ddc_get_phase(self._h, out.ctypes.data), "ddc_get_phase")
+        return out
+
+    def counters(self):
+        a, b, c = _U64(), _U64(), _U64()
+        check(lib().ddc_counters(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "ddc_counters")
+        return a.value, b.value, c.value
+
+    def get_state(self) -> bytes:
+        sz = _SZ(0)
+        check(lib().ddc_get_state(self._h, None, ctypes.byref(sz)), "ddc_get_state")
+        buf = ctypes.create_string_buffer(sz.value)
+        check(lib().ddc_get_state(self._h, buf, ctypes.byref(sz)), "ddc_get_state")
+        return buf.raw[: sz.value]
+
+    def set_state(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().ddc_set_state(self._h, buf, len(blob)), "ddc_set_state")
+
+    def reset(self) -> None:
+        check(lib().ddc_reset(self._h), "ddc_reset")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            check(lib().ddc_destroy(h), "ddc_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,124 @@
+// ddc_kernels.hip -- direct-demodulation bank for gfx950.
+//
+// Paper Sec. III.B demodulates the raw stream against a set of tones, then
+// low-passes and decimates.  For tone t and output n:
+//     y_t[n] = sum_{k<T} h[k] x[m] conj(Tab[phi_t[m] >> 48]),  m = nD + T-1-k,
+//     phi_t[m] = phi0_t + m inc_t (mod 2^64).
+// Writing j = T-1-k and u_n[j] = h[T-1-j] x[nD + j], the tap-weighted input
+// u_n is the same for every tone, so a work-group builds it once in LDS and
+// every lane (one tone each) runs a single complex multiply-accumulate per
+// sample against its own oscillator:
+//     y_t[n] = sum_j u_n[j] conj(c_t[nD + j]).
+// The oscillator is an exact 64-bit integer accumulator.  Its table lookup
+// uses a half-wave sine table in LDS (2^15 FP32 values, 128 KiB):
+//     sin(2 pi i/2^16) = +-S[i mod 2^15]   (sign = bit 15 of i),
+//     cos(2 pi i/2^16) = sin(2 pi (i + 2^14)/2^16),
+// which is bit-identical to the full 2^16-entry table because every entry is
+// the same quarter-wave value q[j] = fp32(sin(pi j/2^15)) with a sign.
+// The input is read from HBM once per output for all tones of a tile.
+#include "fft_device.hpp"
+#include "rf_internal.hpp"
+
+namespace rfk {
+
+__device__ __forceinline__ uint32_t dvload(const VStream &vs, int64_t v)
+{
+    return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
+}
+
+__device__ __forceinline__ float with_sign_of(uint32_t signsrc, float mag)
+{
+    // mag >= 0: OR in bit 31 of signsrc
+    return __uint_as_float((signsrc & 0x80000000u) | __float_as_uint(mag));
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
+{
+    __shared__ float stab[kSinTabLen];
+    __shared__ cf u[4096];
+    const int tid = threadIdx.x;
+
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(a.sintab);
+        float4 *dst = reinterpret_cast<float4 *>(stab);
+        for (int i = tid; i < kSinTabLen / 4; i += WG) dst[i] = src[i];
+    }
+
+    const VStream vs = a.vs;
+    const int T = a.T;
+    const int D = a.D;
+    const int ntones = a.ntones;
+    const int TC = (ntones + WG - 1) / WG;
+    const int64_t nitems = (int64_t)TC * a.nout;
+
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int tc = (int)(it % TC);
+        const int64_t o = it / TC;
+        __syncthreads();  // table loaded; previous item's readers are done with u
+        const int64_t v0 = o * D;
+        for (int j = tid; j < T; j += WG) {
+            cf x = {(float)(int16_t)(dvload(vs, v0 + j) & 0xffffu),
+                    (float)(int16_t)(dvload(vs, v0 + j) >> 16)};
+            const float w = a.wrev[j];
+            u[j] = {w * x.x, w * x.y};
+        }
+        __syncthreads();
+        const int t = tc * WG + tid;
+        if (t < ntones) {
+            const uint64_t inc = a.inc[t];
+            uint64_t ph = a.phi0[t] + (a.base_abs + (uint64_t)v0) * inc;
+            float ar = 0.f, ai = 0.f;
+#pragma unroll 8
+            for (int j = 0; j < T; ++j) {
+                const uint32_t hi = (uint32_t)(ph >> 32);
+                const uint32_t hc = hi + 0x40000000u;  // +quarter turn: cos = sin(. + pi/2)
+                const float s = with_sign_of(hi, stab[(hi >> 16) & 0x7fffu]);
+                const float c = with_sign_of(hc, stab[(hc >> 16) & 0x7fffu]);
+                const cf uu = u[j];
+                // u * conj(c + i s)
+                ar = __builtin_fmaf(uu.x, c, ar);
+                ar = __builtin_fmaf(uu.y, s, ar);
+                ai = __builtin_fmaf(uu.y, c, ai);
+                ai = __builtin_fmaf(-uu.x, s, ai);
+                ph += inc;
+            }
+            float *dst = a.out + 2 * ((int64_t)t * a.ld + o);
+            dst[0] = ar;
+            dst[1] = ai;
+        }
+    }
+
+    if (blockIdx.x == 0)
+        for (int t = tid; t < ntones; t += WG) a.phase_out[t] = a.phi0[t] + a.phase_at * a.inc[t];
+
+    for (int64_t i = (int64_t)blockIdx.x * WG + tid; i < a.keep_len; i += (int64_t)gridDim.x * WG)
+        a.hist_out[i] = dvload(vs, a.keep_from + i);
+}
+
+int ddc_default_grid(int ntones, int64_t nout)
+{
+    (void)ntones;
+    (void)nout;
+    return 256;
+}
+
+template <int WG>
+static hipError_t launch_wg(const DdcLaunch &a, hipStream_t s)
+{
+    int grid = a.grid > 0 ? a.grid : 256;
+    hipLaunchKernelGGL((ddc_bank<WG>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ddc(const DdcLaunch &a, hipStream_t s)
+{
+    if (a.T < 1 || a.T > 4096 || a.D < 1 || a.ntones < 1) return hipErrorInvalidValue;
+    if (a.ntones <= 64) return launch_wg<64>(a, s);
+    if (a.ntones <= 128) return launch_wg<128>(a, s);
+    if (a.ntones <= 256) return launch_wg<256>(a, s);
+    if (a.ntones <= 512) return launch_wg<512>(a, s);
+    return launch_wg<1024>(a, s);
+}
+
+}  // namespace rfk

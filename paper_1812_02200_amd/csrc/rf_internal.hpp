@@ -1,0 +1,65 @@
+// rf_internal.hpp -- launch interface between the C-ABI runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rfk {
+
+// Virtual stream seen by one process call: `hist` (H retained samples) followed
+// by `in` (n new samples); sample v of the virtual stream is hist[v] for v < H,
+// in[v - H] otherwise.  Samples are packed int16 I/Q words (I low, Q high).
+struct VStream {
+    const uint32_t *hist;
+    const uint32_t *in;
+    int64_t H;
+    int64_t n;
+};
+
+struct PfbLaunch {
+    VStream vs;
+    uint32_t *hist_out;     // receives the new history (other ping-pong buffer)
+    int64_t keep_from;      // virtual index of the first retained sample
+    int64_t keep_len;       // number of retained samples
+    float *out;             // [F x N] complex64
+    const float *taps;      // [N*M]
+    const float *tw;        // twiddle tables, float pairs, all passes
+    int64_t F;              // frames to emit
+    int32_t run_len;        // frames per lane-group run (multiple of 4)
+    int32_t N, M;
+};
+
+struct DdcLaunch {
+    VStream vs;
+    uint32_t *hist_out;
+    int64_t keep_from;
+    int64_t keep_len;
+    float *out;             // tone-major, row stride ld complex values
+    int64_t ld;
+    const float *wrev;      // reversed taps: wrev[j] = h[T-1-j]
+    const uint64_t *inc;    // [ntones]
+    const uint64_t *phi0;   // [ntones]
+    const float *sintab;    // half-wave sine table, 2^15 floats
+    uint64_t base_abs;      // absolute sample index of virtual sample 0
+    int64_t nout;           // outputs per tone this call
+    uint64_t *phase_out;    // [ntones]: phi0 + phase_at * inc
+    uint64_t phase_at;
+    int32_t T, D, ntones;
+    int32_t grid;           // work-groups to launch (persistent)
+};
+
+// Twiddle table size (float pairs) for an N-point plan.
+int pfb_twiddle_count(int N);
+// Fill the twiddle table (host memory, float pairs) for an N-point plan.
+void pfb_twiddle_fill(int N, float *tw);
+
+hipError_t launch_pfb(const PfbLaunch &a, hipStream_t s);
+// Frames per run and launch geometry the PFB launcher will use.
+int pfb_default_run_len(int N, int M, int64_t F);
+
+hipError_t launch_ddc(const DdcLaunch &a, hipStream_t s);
+int ddc_default_grid(int ntones, int64_t nout);
+
+// Number of float entries of the half-wave sine table.
+constexpr int kSinTabLen = 1 << 15;
+
+}  // namespace rfk

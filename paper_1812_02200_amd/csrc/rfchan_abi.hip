@@ -1,0 +1,759 @@
+// rfchan_abi.hip -- C ABI, handle state and stream bookkeeping (host side).
+//
+// Host-side counting decides, before any kernel runs, how many frames / outputs
+// a call emits and which samples must be retained; the kernels receive these as
+// plain arguments.  Retained samples live in two device buffers used in turn
+// (the kernel reads one and writes the other), so a process call never waits
+// for the device and never allocates.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/rfchan.h"
+#include "rf_internal.hpp"
+
+#define RF_VERSION (0 * 10000 + 1 * 100 + 0)
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(RF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                    \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) {                \
+            (void)hipGetLastError();           \
+            return hip_fail(e_, what);         \
+        }                                      \
+    } while (0)
+
+// Keeps the caller's current device while a handle's device is made current.
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) {
+            err = hipSetDevice(dev);
+            changed = (err == hipSuccess);
+        }
+    }
+    ~DeviceGuard()
+    {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+// Order this call after the previous call on the same handle when the two
+// name different streams.
+struct StreamOrder {
+    hipStream_t last = nullptr;
+    bool has_last = false;
+    hipEvent_t ev = nullptr;
+
+    int before(hipStream_t s)
+    {
+        if (has_last && last != s) {
+            HIP_TRY(hipEventRecord(ev, last), "hipEventRecord");
+            HIP_TRY(hipStreamWaitEvent(s, ev, 0), "hipStreamWaitEvent");
+        }
+        return RF_OK;
+    }
+    void after(hipStream_t s)
+    {
+        last = s;
+        has_last = true;
+    }
+    int sync()
+    {
+        if (has_last) HIP_TRY(hipStreamSynchronize(last), "hipStreamSynchronize");
+        return RF_OK;
+    }
+};
+
+template <typename T>
+int dev_alloc(T **p, size_t count, const char *what)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? RF_ENOMEM : RF_EDEVICE, "hipMalloc(%s): %s", what,
+                    hipGetErrorString(e));
+    }
+    return RF_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int device_cus(int dev)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+}  // namespace
+
+// ====================================================================== PFB
+
+struct rf_pfb {
+    int N = 0, M = 0, mode = 0;
+    uint64_t max_samples = 0;
+    int device = 0;
+    float *d_taps = nullptr;
+    float *d_tw = nullptr;
+    uint32_t *d_hist[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint64_t S = 0;        // samples received
+    uint64_t frames = 0;   // frames emitted
+    int64_t H = 0;         // retained samples (virtual stream starts at frames*N)
+    int run_len = 0;       // 0: heuristic
+    StreamOrder order;
+};
+
+namespace {
+
+struct PfbStateBlob {
+    uint32_t magic;
+    uint32_t version;
+    int32_t N, M;
+    uint64_t S, frames;
+    int64_t H;
+};
+constexpr uint32_t kPfbMagic = 0x42504652u;  // "RFPB"
+
+void pfb_free(rf_pfb *p)
+{
+    if (!p) return;
+    (void)hipFree(p->d_taps);
+    (void)hipFree(p->d_tw);
+    (void)hipFree(p->d_hist[0]);
+    (void)hipFree(p->d_hist[1]);
+    if (p->order.ev) (void)hipEventDestroy(p->order.ev);
+    delete p;
+}
+
+uint64_t pfb_count(const rf_pfb *p, uint64_t n)
+{
+    const uint64_t vlen = (uint64_t)p->H + n;
+    const uint64_t span = (uint64_t)p->N * p->M;
+    return vlen >= span ? (vlen - span) / p->N + 1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rf_strerror(int status)
+{
+    switch (status) {
+    case RF_OK: return "ok";
+    case RF_EINVAL: return "invalid argument";
+    case RF_ENOMEM: return "out of memory";
+    case RF_EDEVICE: return "HIP runtime error";
+    case RF_ECAPACITY: return "output capacity too small";
+    case RF_EAGAIN: return "resource busy, try again";
+    case RF_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+const char *rf_last_error(void) { return g_last_error.c_str(); }
+
+int rf_version(void) { return RF_VERSION; }
+
+int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, int32_t dft_mode,
+               uint64_t max_samples_per_call)
+{
+    if (!out) return fail(RF_EINVAL, "pfb_create: out is NULL");
+    *out = nullptr;
+    if (nchan < 16 || nchan > 4096 || (nchan & (nchan - 1)))
+        return fail(RF_EINVAL, "pfb_create: nchan=%d must be a power of two in [16, 4096]", nchan);
+    if (ntaps < 1 || ntaps > 16) return fail(RF_EINVAL, "pfb_create: ntaps=%d must be in [1, 16]", ntaps);
+    if (!proto) return fail(RF_EINVAL, "pfb_create: proto is NULL");
+    if (max_samples_per_call < 1 || max_samples_per_call > (1ull << 40))
+        return fail(RF_EINVAL, "pfb_create: max_samples_per_call out of range");
+    if (dft_mode != RF_DFT_FFT_F32 && dft_mode != RF_DFT_MFMA_F16X2 && dft_mode != RF_DFT_MFMA_BF16X2)
+        return fail(RF_EINVAL, "pfb_create: unknown dft_mode %d", dft_mode);
+    if (dft_mode != RF_DFT_FFT_F32)
+        return fail(RF_EUNSUPPORTED, "pfb_create: MFMA DFT modes are not built in this version");
+    for (int i = 0; i < nchan * ntaps; ++i)
+        if (!isfinite(proto[i])) return fail(RF_EINVAL, "pfb_create: proto[%d] is not finite", i);
+
+    rf_pfb *p = new (std::nothrow) rf_pfb;
+    if (!p) return fail(RF_ENOMEM, "pfb_create: host allocation");
+    p->N = nchan;
+    p->M = ntaps;
+    p->mode = dft_mode;
+    p->max_samples = max_samples_per_call;
+    int rc = RF_OK;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        pfb_free(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    const size_t span = (size_t)nchan * ntaps;
+    const int ntw = rfk::pfb_twiddle_count(nchan);
+    float *tw = (float *)malloc(sizeof(float) * 2 * ntw);
+    if (!tw) {
+        pfb_free(p);
+        return fail(RF_ENOMEM, "pfb_create: host allocation");
+    }
+    rfk::pfb_twiddle_fill(nchan, tw);
+    if ((rc = dev_alloc(&p->d_taps, span, "taps")) || (rc = dev_alloc(&p->d_tw, 2 * (size_t)ntw, "twiddles")) ||
+        (rc = dev_alloc(&p->d_hist[0], span, "history")) || (rc = dev_alloc(&p->d_hist[1], span, "history"))) {
+        free(tw);
+        pfb_free(p);
+        return rc;
+    }
+    e = hipMemcpy(p->d_taps, proto, span * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw, sizeof(float) * 2 * ntw, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);
+    free(tw);
+    if (e != hipSuccess) {
+        pfb_free(p);
+        return hip_fail(e, "pfb_create");
+    }
+    const char *rl = getenv("RFCHAN_PFB_RUN_LEN");
+    if (rl) {
+        int v = atoi(rl);
+        if (v >= 4 && v % 4 == 0) p->run_len = v;
+    }
+    *out = p;
+    return RF_OK;
+}
+
+uint64_t pfb_frames_for(rf_pfb_t pfb, uint64_t nsamples)
+{
+    if (!pfb) return 0;
+    return pfb_count(pfb, nsamples);
+}
+
+int pfb_process(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out_dev, uint64_t out_cap_frames,
+                uint64_t *frames_out, void *hip_stream)
+{
+    if (frames_out) *frames_out = 0;
+    if (!p) return fail(RF_EINVAL, "pfb_process: handle is NULL");
+    if (nsamples > p->max_samples)
+        return fail(RF_EINVAL, "pfb_process: nsamples=%llu exceeds max_samples_per_call=%llu",
+                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
+    if (nsamples > 0 && (!iq_dev || !aligned(iq_dev, 4)))
+        return fail(RF_EINVAL, "pfb_process: iq_dev must be a non-NULL 4-byte aligned device pointer");
+    const uint64_t F = pfb_count(p, nsamples);
+    if (F > out_cap_frames)
+        return fail(RF_ECAPACITY, "pfb_process: %llu frames need more than out_cap_frames=%llu",
+                    (unsigned long long)F, (unsigned long long)out_cap_frames);
+    if (F > 0 && (!out_dev || !aligned(out_dev, 8)))
+        return fail(RF_EINVAL, "pfb_process: out_dev must be a non-NULL 8-byte aligned device pointer");
+    if (nsamples == 0) return RF_OK;
+
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = p->order.before(s);
+    if (rc) return rc;
+
+    const int64_t vlen = p->H + (int64_t)nsamples;
+    rfk::PfbLaunch a;
+    a.vs.hist = p->d_hist[p->cur];
+    a.vs.in = reinterpret_cast<const uint32_t *>(iq_dev);
+    a.vs.H = p->H;
+    a.vs.n = (int64_t)nsamples;
+    a.hist_out = p->d_hist[p->cur ^ 1];
+    a.keep_from = (int64_t)F * p->N;
+    a.keep_len = vlen - a.keep_from;
+    a.out = out_dev;
+    a.taps = p->d_taps;
+    a.tw = p->d_tw;
+    a.F = (int64_t)F;
+    a.run_len = p->run_len > 0 ? p->run_len : rfk::pfb_default_run_len(p->N, p->M, (int64_t)F);
+    a.N = p->N;
+    a.M = p->M;
+    HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
+
+    p->order.after(s);
+    p->cur ^= 1;
+    p->H = a.keep_len;
+    p->S += nsamples;
+    p->frames += F;
+    if (frames_out) *frames_out = F;
+    return RF_OK;
+}
+
+int pfb_counters(rf_pfb_t p, uint64_t *samples_in, uint64_t *frames_out, uint64_t *history_samples)
+{
+    if (!p) return fail(RF_EINVAL, "pfb_counters: handle is NULL");
+    if (samples_in) *samples_in = p->S;
+    if (frames_out) *frames_out = p->frames;
+    if (history_samples) *history_samples = (uint64_t)p->H;
+    return RF_OK;
+}
+
+int pfb_get_state(rf_pfb_t p, void *blob, size_t *size)
+{
+    if (!p || !size) return fail(RF_EINVAL, "pfb_get_state: NULL argument");
+    const size_t need = sizeof(PfbStateBlob) + (size_t)p->H * 4;
+    if (!blob) {
+        *size = need;
+        return RF_OK;
+    }
+    if (*size < need) {
+        *size = need;
+        return fail(RF_ECAPACITY, "pfb_get_state: blob needs %zu bytes", need);
+    }
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    PfbStateBlob h = {kPfbMagic, 1, p->N, p->M, p->S, p->frames, p->H};
+    memcpy(blob, &h, sizeof h);
+    if (p->H > 0)
+        HIP_TRY(hipMemcpy((char *)blob + sizeof h, p->d_hist[p->cur], (size_t)p->H * 4, hipMemcpyDeviceToHost),
+                "hipMemcpy(state)");
+    *size = need;
+    return RF_OK;
+}
+
+int pfb_set_state(rf_pfb_t p, const void *blob, size_t size)
+{
+    if (!p || !blob) return fail(RF_EINVAL, "pfb_set_state: NULL argument");
+    PfbStateBlob h;
+    if (size < sizeof h) return fail(RF_EINVAL, "pfb_set_state: blob too small");
+    memcpy(&h, blob, sizeof h);
+    if (h.magic != kPfbMagic || h.version != 1) return fail(RF_EINVAL, "pfb_set_state: not a PFB state blob");
+    if (h.N != p->N || h.M != p->M) return fail(RF_EINVAL, "pfb_set_state: blob is for N=%d M=%d", h.N, h.M);
+    if (h.H < 0 || h.H >= (int64_t)p->N * p->M || size < sizeof h + (size_t)h.H * 4)
+        return fail(RF_EINVAL, "pfb_set_state: inconsistent history length");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    if (h.H > 0)
+        HIP_TRY(hipMemcpy(p->d_hist[p->cur], (const char *)blob + sizeof h, (size_t)h.H * 4, hipMemcpyHostToDevice),
+                "hipMemcpy(state)");
+    p->S = h.S;
+    p->frames = h.frames;
+    p->H = h.H;
+    return RF_OK;
+}
+
+int pfb_reset(rf_pfb_t p)
+{
+    if (!p) return fail(RF_EINVAL, "pfb_reset: handle is NULL");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    p->S = 0;
+    p->frames = 0;
+    p->H = 0;
+    return RF_OK;
+}
+
+int pfb_destroy(rf_pfb_t p)
+{
+    if (!p) return RF_OK;
+    int rc = RF_OK;
+    {
+        DeviceGuard dg(p->device);
+        if (dg.err == hipSuccess) rc = p->order.sync();
+        pfb_free(p);
+    }
+    return rc;
+}
+
+}  // extern "C"
+
+// ====================================================================== DDC
+
+struct rf_ddc {
+    int ntones = 0, T = 0, D = 0;
+    uint64_t max_samples = 0;
+    int device = 0;
+    int cus = 256;
+    uint64_t *d_inc = nullptr, *d_phi0 = nullptr, *d_phase = nullptr;
+    float *d_wrev = nullptr, *d_tab = nullptr;
+    uint32_t *d_hist[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint64_t S = 0;       // samples received
+    uint64_t nnext = 0;   // outputs emitted (absolute index of the next output)
+    int64_t H = 0;        // retained samples, absolute [S-H, S) == [nnext*D, S)
+    uint64_t skip = 0;    // samples of future input before nnext*D (only when D > T)
+    uint64_t *h_inc = nullptr, *h_phi0 = nullptr;
+    float *h_taps = nullptr;
+    int grid = 0;
+    StreamOrder order;
+};
+
+namespace {
+
+struct DdcStateBlob {
+    uint32_t magic;
+    uint32_t version;
+    int32_t ntones, T, D, pad;
+    uint64_t S, nnext, skip;
+    int64_t H;
+    uint64_t fingerprint;
+};
+constexpr uint32_t kDdcMagic = 0x43444652u;  // "RFDC"
+
+void ddc_free(rf_ddc *p)
+{
+    if (!p) return;
+    (void)hipFree(p->d_inc);
+    (void)hipFree(p->d_phi0);
+    (void)hipFree(p->d_phase);
+    (void)hipFree(p->d_wrev);
+    (void)hipFree(p->d_tab);
+    (void)hipFree(p->d_hist[0]);
+    (void)hipFree(p->d_hist[1]);
+    if (p->order.ev) (void)hipEventDestroy(p->order.ev);
+    free(p->h_inc);
+    free(p->h_phi0);
+    free(p->h_taps);
+    delete p;
+}
+
+// FNV-1a over the configuration, so a state blob only restores onto the same bank.
+uint64_t ddc_fingerprint(const rf_ddc *p)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *d, size_t n) {
+        const unsigned char *c = (const unsigned char *)d;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= c[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(&p->ntones, sizeof p->ntones);
+    mix(&p->T, sizeof p->T);
+    mix(&p->D, sizeof p->D);
+    mix(p->h_inc, sizeof(uint64_t) * p->ntones);
+    mix(p->h_phi0, sizeof(uint64_t) * p->ntones);
+    mix(p->h_taps, sizeof(float) * p->T);
+    return h;
+}
+
+struct DdcPlan {
+    uint64_t nskip, neff, nout, keep_from, keep_len, skip_after;
+};
+
+DdcPlan ddc_plan(const rf_ddc *p, uint64_t n)
+{
+    DdcPlan r{};
+    r.nskip = p->skip < n ? p->skip : n;
+    r.neff = n - r.nskip;
+    const uint64_t vlen = (uint64_t)p->H + r.neff;
+    if (p->skip > n) {
+        r.skip_after = p->skip - n;
+        return r;
+    }
+    r.nout = vlen >= (uint64_t)p->T ? (vlen - p->T) / p->D + 1 : 0;
+    const uint64_t consumed = r.nout * (uint64_t)p->D;
+    if (consumed <= vlen) {
+        r.keep_from = consumed;
+        r.keep_len = vlen - consumed;
+    } else {
+        r.skip_after = consumed - vlen;
+    }
+    return r;
+}
+
+// Half-wave sine table: S[i] = sin(2 pi i / 2^16), i in [0, 2^15), built from
+// the quarter wave q[j] = fp32(sin(pi j / 2^15)) so every entry equals the
+// corresponding entry of the full FP32 table up to sign.
+void fill_sintab(float *tab)
+{
+    const double pi = 3.14159265358979323846264338327950288;
+    for (int i = 0; i < rfk::kSinTabLen; ++i) {
+        int j = i <= (1 << 14) ? i : (1 << 15) - i;
+        tab[i] = (float)sin(pi * (double)j / 32768.0);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const uint64_t *phase0, int32_t ntaps,
+               const float *lpf, int32_t decim, uint64_t max_samples_per_call)
+{
+    if (!out) return fail(RF_EINVAL, "ddc_create: out is NULL");
+    *out = nullptr;
+    if (ntones < 1 || ntones > 65536) return fail(RF_EINVAL, "ddc_create: ntones=%d must be in [1, 65536]", ntones);
+    if (!phase_inc) return fail(RF_EINVAL, "ddc_create: phase_inc is NULL");
+    if (ntaps < 1 || ntaps > 4096) return fail(RF_EINVAL, "ddc_create: ntaps=%d must be in [1, 4096]", ntaps);
+    if (!lpf) return fail(RF_EINVAL, "ddc_create: lpf is NULL");
+    if (decim < 1 || decim > (1 << 20)) return fail(RF_EINVAL, "ddc_create: decim=%d must be in [1, 2^20]", decim);
+    if (max_samples_per_call < 1 || max_samples_per_call > (1ull << 40))
+        return fail(RF_EINVAL, "ddc_create: max_samples_per_call out of range");
+    for (int i = 0; i < ntaps; ++i)
+        if (!isfinite(lpf[i])) return fail(RF_EINVAL, "ddc_create: lpf[%d] is not finite", i);
+
+    rf_ddc *p = new (std::nothrow) rf_ddc;
+    if (!p) return fail(RF_ENOMEM, "ddc_create: host allocation");
+    p->ntones = ntones;
+    p->T = ntaps;
+    p->D = decim;
+    p->max_samples = max_samples_per_call;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        ddc_free(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    p->cus = device_cus(p->device);
+    p->h_inc = (uint64_t *)malloc(sizeof(uint64_t) * ntones);
+    p->h_phi0 = (uint64_t *)calloc(ntones, sizeof(uint64_t));
+    p->h_taps = (float *)malloc(sizeof(float) * ntaps);
+    float *wrev = (float *)malloc(sizeof(float) * ntaps);
+    float *tab = (float *)malloc(sizeof(float) * rfk::kSinTabLen);
+    if (!p->h_inc || !p->h_phi0 || !p->h_taps || !wrev || !tab) {
+        free(wrev);
+        free(tab);
+        ddc_free(p);
+        return fail(RF_ENOMEM, "ddc_create: host allocation");
+    }
+    memcpy(p->h_inc, phase_inc, sizeof(uint64_t) * ntones);
+    if (phase0) memcpy(p->h_phi0, phase0, sizeof(uint64_t) * ntones);
+    memcpy(p->h_taps, lpf, sizeof(float) * ntaps);
+    for (int j = 0; j < ntaps; ++j) wrev[j] = lpf[ntaps - 1 - j];
+    fill_sintab(tab);
+    int rc = RF_OK;
+    const size_t hist_len = (size_t)ntaps;
+    if ((rc = dev_alloc(&p->d_inc, ntones, "inc")) || (rc = dev_alloc(&p->d_phi0, ntones, "phi0")) ||
+        (rc = dev_alloc(&p->d_phase, ntones, "phase")) || (rc = dev_alloc(&p->d_wrev, ntaps, "taps")) ||
+        (rc = dev_alloc(&p->d_tab, rfk::kSinTabLen, "table")) ||
+        (rc = dev_alloc(&p->d_hist[0], hist_len, "history")) ||
+        (rc = dev_alloc(&p->d_hist[1], hist_len, "history"))) {
+        free(wrev);
+        free(tab);
+        ddc_free(p);
+        return rc;
+    }
+    e = hipMemcpy(p->d_inc, p->h_inc, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_phi0, p->h_phi0, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_phase, p->h_phi0, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_wrev, wrev, sizeof(float) * ntaps, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab, sizeof(float) * rfk::kSinTabLen, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);
+    free(wrev);
+    free(tab);
+    if (e != hipSuccess) {
+        ddc_free(p);
+        return hip_fail(e, "ddc_create");
+    }
+    const char *g = getenv("RFCHAN_DDC_GRID");
+    if (g) p->grid = atoi(g);
+    *out = p;
+    return RF_OK;
+}
+
+uint64_t ddc_outputs_for(rf_ddc_t p, uint64_t nsamples)
+{
+    if (!p) return 0;
+    return ddc_plan(p, nsamples).nout;
+}
+
+int ddc_process(rf_ddc_t p, const int16_t *iq_dev, uint64_t nsamples, float *out_dev, uint64_t ld, uint64_t *nout,
+                void *hip_stream)
+{
+    if (nout) *nout = 0;
+    if (!p) return fail(RF_EINVAL, "ddc_process: handle is NULL");
+    if (nsamples > p->max_samples)
+        return fail(RF_EINVAL, "ddc_process: nsamples=%llu exceeds max_samples_per_call=%llu",
+                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
+    if (nsamples > 0 && (!iq_dev || !aligned(iq_dev, 4)))
+        return fail(RF_EINVAL, "ddc_process: iq_dev must be a non-NULL 4-byte aligned device pointer");
+    const DdcPlan pl = ddc_plan(p, nsamples);
+    if (pl.nout > 0) {
+        if (ld < pl.nout)
+            return fail(RF_ECAPACITY, "ddc_process: ld=%llu < %llu outputs", (unsigned long long)ld,
+                        (unsigned long long)pl.nout);
+        if (!out_dev || !aligned(out_dev, 8))
+            return fail(RF_EINVAL, "ddc_process: out_dev must be a non-NULL 8-byte aligned device pointer");
+    }
+    if (nsamples == 0) return RF_OK;
+
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = p->order.before(s);
+    if (rc) return rc;
+
+    rfk::DdcLaunch a;
+    a.vs.hist = p->d_hist[p->cur];
+    a.vs.in = reinterpret_cast<const uint32_t *>(iq_dev) + pl.nskip;
+    a.vs.H = p->skip > 0 ? 0 : p->H;
+    a.vs.n = (int64_t)pl.neff;
+    a.hist_out = p->d_hist[p->cur ^ 1];
+    a.keep_from = (int64_t)pl.keep_from;
+    a.keep_len = (int64_t)pl.keep_len;
+    a.out = out_dev;
+    a.ld = (int64_t)ld;
+    a.wrev = p->d_wrev;
+    a.inc = p->d_inc;
+    a.phi0 = p->d_phi0;
+    a.sintab = p->d_tab;
+    a.base_abs = p->nnext * (uint64_t)p->D;
+    a.nout = (int64_t)pl.nout;
+    a.phase_out = p->d_phase;
+    a.phase_at = p->S + nsamples;
+    a.T = p->T;
+    a.D = p->D;
+    a.ntones = p->ntones;
+    {
+        const int wg = p->ntones <= 64 ? 64 : p->ntones <= 128 ? 128 : p->ntones <= 256 ? 256
+                       : p->ntones <= 512 ? 512 : 1024;
+        const int64_t tc = (p->ntones + wg - 1) / wg;
+        int64_t items = tc * (int64_t)pl.nout;
+        int64_t grid = p->grid > 0 ? p->grid : p->cus;
+        if (grid > items) grid = items;
+        if (grid < 1) grid = 1;
+        a.grid = (int32_t)grid;
+    }
+    HIP_TRY(rfk::launch_ddc(a, s), "ddc kernel launch");
+
+    p->order.after(s);
+    p->cur ^= 1;
+    p->S += nsamples;
+    p->nnext += pl.nout;
+    p->H = (int64_t)pl.keep_len;
+    p->skip = pl.skip_after;
+    if (nout) *nout = pl.nout;
+    return RF_OK;
+}
+
+int ddc_get_phase(rf_ddc_t p, uint64_t *phase_host)
+{
+    if (!p || !phase_host) return fail(RF_EINVAL, "ddc_get_phase: NULL argument");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(phase_host, p->d_phase, sizeof(uint64_t) * p->ntones, hipMemcpyDeviceToHost),
+            "hipMemcpy(phase)");
+    return RF_OK;
+}
+
+int ddc_counters(rf_ddc_t p, uint64_t *samples_in, uint64_t *outputs_out, uint64_t *history_samples)
+{
+    if (!p) return fail(RF_EINVAL, "ddc_counters: handle is NULL");
+    if (samples_in) *samples_in = p->S;
+    if (outputs_out) *outputs_out = p->nnext;
+    if (history_samples) *history_samples = (uint64_t)p->H;
+    return RF_OK;
+}
+
+int ddc_get_state(rf_ddc_t p, void *blob, size_t *size)
+{
+    if (!p || !size) return fail(RF_EINVAL, "ddc_get_state: NULL argument");
+    const size_t need = sizeof(DdcStateBlob) + (size_t)p->H * 4;
+    if (!blob) {
+        *size = need;
+        return RF_OK;
+    }
+    if (*size < need) {
+        *size = need;
+        return fail(RF_ECAPACITY, "ddc_get_state: blob needs %zu bytes", need);
+    }
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    DdcStateBlob h = {kDdcMagic, 1, p->ntones, p->T, p->D, 0, p->S, p->nnext, p->skip, p->H, ddc_fingerprint(p)};
+    memcpy(blob, &h, sizeof h);
+    if (p->H > 0)
+        HIP_TRY(hipMemcpy((char *)blob + sizeof h, p->d_hist[p->cur], (size_t)p->H * 4, hipMemcpyDeviceToHost),
+                "hipMemcpy(state)");
+    *size = need;
+    return RF_OK;
+}
+
+int ddc_set_state(rf_ddc_t p, const void *blob, size_t size)
+{
+    if (!p || !blob) return fail(RF_EINVAL, "ddc_set_state: NULL argument");
+    DdcStateBlob h;
+    if (size < sizeof h) return fail(RF_EINVAL, "ddc_set_state: blob too small");
+    memcpy(&h, blob, sizeof h);
+    if (h.magic != kDdcMagic || h.version != 1) return fail(RF_EINVAL, "ddc_set_state: not a DDC state blob");
+    if (h.fingerprint != ddc_fingerprint(p)) return fail(RF_EINVAL, "ddc_set_state: blob is for another bank");
+    if (h.H < 0 || h.H >= p->T || size < sizeof h + (size_t)h.H * 4)
+        return fail(RF_EINVAL, "ddc_set_state: inconsistent history length");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    if (h.H > 0)
+        HIP_TRY(hipMemcpy(p->d_hist[p->cur], (const char *)blob + sizeof h, (size_t)h.H * 4, hipMemcpyHostToDevice),
+                "hipMemcpy(state)");
+    // phase of the next sample follows from the sample count
+    uint64_t *ph = (uint64_t *)malloc(sizeof(uint64_t) * p->ntones);
+    if (!ph) return fail(RF_ENOMEM, "ddc_set_state: host allocation");
+    for (int t = 0; t < p->ntones; ++t) ph[t] = p->h_phi0[t] + h.S * p->h_inc[t];
+    hipError_t e = hipMemcpy(p->d_phase, ph, sizeof(uint64_t) * p->ntones, hipMemcpyHostToDevice);
+    free(ph);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase)");
+    p->S = h.S;
+    p->nnext = h.nnext;
+    p->skip = h.skip;
+    p->H = h.H;
+    return RF_OK;
+}
+
+int ddc_reset(rf_ddc_t p)
+{
+    if (!p) return fail(RF_EINVAL, "ddc_reset: handle is NULL");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(p->d_phase, p->h_phi0, sizeof(uint64_t) * p->ntones, hipMemcpyHostToDevice),
+            "hipMemcpy(phase)");
+    p->S = 0;
+    p->nnext = 0;
+    p->H = 0;
+    p->skip = 0;
+    return RF_OK;
+}
+
+int ddc_destroy(rf_ddc_t p)
+{
+    if (!p) return RF_OK;
+    int rc = RF_OK;
+    {
+        DeviceGuard dg(p->device);
+        if (dg.err == hipSuccess) rc = p->order.sync();
+        ddc_free(p);
+    }
+    return rc;
+}
+
+}  // extern "C"
