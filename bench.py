@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the readout hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|pfb|ddc]
+
+One step is one pass of the hot path over one batch of synthetic input:
+  * PFB: N=1024 channels, M=8 taps, Kaiser(9)-sinc prototype, 2^28 int16 I/Q
+    samples in 16 buffers of 2^24 (one pfb_process call per buffer), FIR
+    history carried across buffers and steps (a continuous stream);
+  * DDC: 1000 tones, 1024-tap Blackman-sinc low-pass, decimation 1000, 2^27
+    samples in 16 buffers of 2^23, NCO phase and FIR history carried.
+Inputs are generated on the device before timing and stay resident in HBM.
+`value` is the PFB's sustained input rate (Msamples/s); the DDC's figures are
+in the "ddc" object.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector, published (packed FP32 included)
+METRIC = "sustained Msamples/s (N=1024 PFB, 1000-tone DDC) + p99 buffer latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="all", choices=["all", "pfb", "ddc"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate CPU time budget per oracle baseline sample")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ PFB
+
+def bench_pfb(rf, torch, siggen, steps, warmup):
+    w = siggen.pfb_production()
+    log("pfb: generating %d samples on the device" % w.nsamples)
+    d = siggen.iq_torch(w.stream, 0, w.nsamples)
+    nbuf = w.nsamples // w.buffer
+    fpb = w.buffer // w.N                           # frames per buffer in steady state
+    out = torch.empty((nbuf, fpb, w.N), dtype=torch.complex64, device="cuda")
+    p = rf.Pfb(w.N, w.M, w.h, max_samples_per_call=w.buffer)
+    s = torch.cuda.current_stream()
+    sh = s.cuda_stream
+    base_in, base_out = d.data_ptr(), out.data_ptr()
+    frames = [0]
+
+    def step():
+        for b in range(nbuf):
+            frames[0] += p.process_ptr(base_in + 4 * b * w.buffer, w.buffer,
+                                       base_out + 8 * b * fpb * w.N, fpb, sh)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    f0 = frames[0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    launches = steps * nbuf
+    samples = steps * w.nsamples
+    kern_s = ms / 1e3 / launches
+    bytes_per_launch = 12.0 * w.buffer                  # 4 B in + 8 B out per sample
+    achieved = bytes_per_launch / kern_s / 1e9
+    res = {
+        "value": samples / (ms / 1e3) / 1e6,
+        "ms_per_step": ms / steps,
+        "wall_ms_per_step": wall * 1e3 / steps,
+        "frames_per_step": (frames[0] - f0) / steps,
+        "kernel_us": kern_s * 1e6,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "per_launch": "12 B x 2^24 samples = %.1f MB" % (bytes_per_launch / 1e6)},
+        "config": {"workload": w.name + ", 2^28 int16 I/Q samples in 2^24-sample buffers",
+                   "N": w.N, "M": w.M, "buffer_samples": w.buffer, "samples_per_step": w.nsamples},
+    }
+    return res, (w, d)
+
+
+def cpu_pfb(oracle, w, d, budget_s):
+    """The FP64 oracle on a bounded sample of the same stream (host cores)."""
+    nf = 256
+    iq = d[: 2 * (nf + w.M) * w.N].cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.pfb(w.h, w.N, w.M, iq=iq, frames=np.arange(nf))
+    t = time.perf_counter() - t0
+    nf = int(min(16384, max(nf, nf * budget_s / max(t, 1e-6))))
+    iq = d[: 2 * (nf + w.M) * w.N].cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.pfb(w.h, w.N, w.M, iq=iq, frames=np.arange(nf))
+    t = time.perf_counter() - t0
+    return {"value": nf * w.N / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": t,
+            "sample": "%d frames (%d samples) of the N=1024 M=8 stream, FP64, OpenMP over frames"
+                      % (nf, nf * w.N)}
+
+
+# ------------------------------------------------------------------ DDC
+
+def bench_ddc(rf, torch, siggen, steps, warmup):
+    w = siggen.ddc_bank()
+    log("ddc: generating %d samples on the device" % w.nsamples)
+    d = siggen.iq_torch(w.stream, 0, w.nsamples)
+    nbuf = w.nsamples // w.buffer
+    ld = w.buffer // w.D + 2
+    out = torch.empty((nbuf, w.words.size, ld), dtype=torch.complex64, device="cuda")
+    dd = rf.Ddc(w.words, w.h, w.D, w.phase0, max_samples_per_call=w.buffer)
+    s = torch.cuda.current_stream()
+    sh = s.cuda_stream
+    base_in, base_out = d.data_ptr(), out.data_ptr()
+    nout = [0]
+
+    def step():
+        for b in range(nbuf):
+            nout[0] += dd.process_ptr(base_in + 4 * b * w.buffer, w.buffer,
+                                      base_out + 8 * b * w.words.size * ld, ld, sh)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    n0 = nout[0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    outs = (nout[0] - n0)
+    launches = steps * nbuf
+    kern_s = ms / 1e3 / launches
+    flop = 8.0 * w.h.size * w.words.size * outs / launches    # one complex MAC per tap-tone
+    achieved = flop / kern_s / 1e12
+    return {
+        "value": steps * w.nsamples / (ms / 1e3) / 1e6,
+        "unit": "Msamples/s",
+        "ms_per_step": ms / steps,
+        "kernel_us": kern_s * 1e6,
+        "outputs_per_tone_per_step": outs / steps,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TF,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TF, "traffic": None,
+                     "per_launch": "8 flop x 1024 taps x 1000 tones x %.1f outputs" % (outs / launches)},
+        "config": {"workload": w.name + ", 2^27 int16 I/Q samples in 2^23-sample buffers",
+                   "ntones": int(w.words.size), "T": int(w.h.size), "D": w.D,
+                   "buffer_samples": w.buffer},
+    }, (w, d)
+
+
+def cpu_ddc(oracle, w, d, budget_s):
+    iq = d[: 2 * (w.buffer)].cpu().numpy()
+    nout = oracle.ddc_noutputs(w.buffer, w.h.size, w.D)
+    ntones = w.words.size
+
+    def run(k):
+        ti = np.repeat(np.arange(ntones), k)
+        oi = np.tile(np.arange(k), ntones)
+        t0 = time.perf_counter()
+        oracle.ddc_points(w.words, w.phase0, w.h, w.D, ti, oi, iq=iq)
+        return time.perf_counter() - t0
+
+    t = run(1)
+    k = int(min(nout, max(1, budget_s / max(t, 1e-6))))
+    t = run(k)
+    # k outputs of every tone cover k*D input samples of the 1000-tone bank
+    return {"value": k * w.D / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": t,
+            "sample": "%d outputs x %d tones (%d input samples), FP64, OpenMP over points"
+                      % (k, ntones, k * w.D)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported" % a.gpus}))
+        sys.exit(2)
+    import torch
+    import siggen
+    import paper_1812_02200_amd as rf
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    rec = {"metric": METRIC, "value": None, "unit": "Msamples/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {}, "device": torch.cuda.get_device_name(0)}
+    keep = {}
+    if a.workload in ("all", "pfb"):
+        r, keep["pfb"] = bench_pfb(rf, torch, siggen, a.steps, a.warmup)
+        rec["value"] = r["value"]
+        rec["ms_per_step"] = r["ms_per_step"]
+        rec["config"] = r.pop("config")
+        rec["roofline"] = r.pop("roofline")
+        rec["pfb"] = r
+        log("pfb: %.0f Msamples/s, %.1f us/launch" % (r["value"], r["kernel_us"]))
+    if a.workload in ("all", "ddc"):
+        r, keep["ddc"] = bench_ddc(rf, torch, siggen, a.steps, a.warmup)
+        rec["ddc"] = r
+        if rec["value"] is None:
+            rec["value"] = r["value"]
+            rec["ms_per_step"] = r["ms_per_step"]
+            rec["config"] = r["config"]
+            rec["roofline"] = r["roofline"]
+        log("ddc: %.0f Msamples/s, %.1f us/launch" % (r["value"], r["kernel_us"]))
+    if not a.no_cpu_baseline:
+        import oracle
+        if "pfb" in keep:
+            rec["cpu_baseline"] = cpu_pfb(oracle, *keep["pfb"], a.cpu_seconds)
+        if "ddc" in keep:
+            cb = cpu_ddc(oracle, *keep["ddc"], a.cpu_seconds)
+            if "cpu_baseline" in rec:
+                rec["ddc"]["cpu_baseline"] = cb
+            else:
+                rec["cpu_baseline"] = cb
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

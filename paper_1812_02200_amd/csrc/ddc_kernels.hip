@@ -68,24 +68,33 @@ __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
         if (t < ntones) {
             const uint64_t inc = a.inc[t];
             uint64_t ph = a.phi0[t] + (a.base_abs + (uint64_t)v0) * inc;
-            float ar = 0.f, ai = 0.f;
-#pragma unroll 8
-            for (int j = 0; j < T; ++j) {
+            // four interleaved partial sums (j mod 4): independent FMA chains
+            float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+            auto mac = [&](int q, int j) {
                 const uint32_t hi = (uint32_t)(ph >> 32);
                 const uint32_t hc = hi + 0x40000000u;  // +quarter turn: cos = sin(. + pi/2)
                 const float s = with_sign_of(hi, stab[(hi >> 16) & 0x7fffu]);
                 const float c = with_sign_of(hc, stab[(hc >> 16) & 0x7fffu]);
                 const cf uu = u[j];
                 // u * conj(c + i s)
-                ar = __builtin_fmaf(uu.x, c, ar);
-                ar = __builtin_fmaf(uu.y, s, ar);
-                ai = __builtin_fmaf(uu.y, c, ai);
-                ai = __builtin_fmaf(-uu.x, s, ai);
+                ar[q] = __builtin_fmaf(uu.x, c, ar[q]);
+                ar[q] = __builtin_fmaf(uu.y, s, ar[q]);
+                ai[q] = __builtin_fmaf(uu.y, c, ai[q]);
+                ai[q] = __builtin_fmaf(-uu.x, s, ai[q]);
                 ph += inc;
+            };
+            const int T4 = T & ~3;
+#pragma unroll 2
+            for (int j = 0; j < T4; j += 4) {
+                mac(0, j);
+                mac(1, j + 1);
+                mac(2, j + 2);
+                mac(3, j + 3);
             }
+            for (int j = T4; j < T; ++j) mac(j & 3, j);
             float *dst = a.out + 2 * ((int64_t)t * a.ld + o);
-            dst[0] = ar;
-            dst[1] = ai;
+            dst[0] = (ar[0] + ar[1]) + (ar[2] + ar[3]);
+            dst[1] = (ai[0] + ai[1]) + (ai[2] + ai[3]);
         }
     }
 

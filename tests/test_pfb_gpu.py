@@ -1,0 +1,233 @@
+"""GPU parity of the PFB channelizer (pfb_* C ABI) against the FP64 oracle.
+
+Bar: RMS error <= 1e-5 of a full-scale tone's output (8192 * sum h), and as a
+regression guard ||e|| / ||y_ref|| <= 1e-6.  Split invariance and state resume
+are bit-exact (every frame is computed by the same instruction sequence
+whatever the buffer boundaries).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import siggen
+from gpu_util import err_fs, err_rel, f32, log, need_gpu, run_pfb, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_FS = 1e-5
+TOL_REL = 1e-6
+
+
+def _rf():
+    need_gpu()
+    import paper_1812_02200_amd as rf
+    return rf
+
+
+def test_pfb_small_workload_parity():
+    """N=64, M=4, Hann prototype, 2^20 samples in one call -> 16381 frames."""
+    rf = _rf()
+    import torch
+    w = siggen.pfb_small()
+    iq = w.stream.iq(0, w.nsamples)
+    log("pfb small workload: N=64 M=4 S=2^20")
+    p = rf.Pfb(w.N, w.M, w.h, max_samples_per_call=w.nsamples)
+    y = run_pfb(p, to_dev(iq), [w.nsamples], torch)
+    assert y.shape == (16381, 64)
+    ref = oracle.pfb(f32(w.h), w.N, w.M, iq=iq)
+    e, r = err_fs(y, ref, w.h.sum()), err_rel(y, ref)
+    log("err_fs=%.3g err_rel=%.3g" % (e, r))
+    assert e <= TOL_FS and r <= TOL_REL
+
+
+SHAPES = [(16, 1), (16, 4), (32, 3), (64, 2), (64, 8), (128, 5), (256, 8), (256, 16),
+          (512, 4), (1024, 1), (1024, 8), (1024, 16), (2048, 6), (4096, 4), (4096, 8)]
+
+
+@pytest.mark.parametrize("N,M", SHAPES)
+def test_pfb_parity_all_shapes(N, M):
+    """Several runs of frames per work-group and a ragged tail, one call."""
+    rf = _rf()
+    import torch
+    h = siggen.pfb_prototype(N, M, "kaiser", 9.0)
+    nfr = 150 if N <= 1024 else 40
+    n = N * (M - 1) + N * nfr + 7      # ragged tail shorter than one frame hop
+    spec = siggen.StreamSpec(11, siggen.pfb_small().stream.tones, 700.0)
+    iq = spec.iq(0, n)
+    log("pfb parity N=%d M=%d n=%d" % (N, M, n))
+    p = rf.Pfb(N, M, h, max_samples_per_call=n)
+    y = run_pfb(p, to_dev(iq), [n], torch)
+    ref = oracle.pfb(f32(h), N, M, iq=iq)
+    assert y.shape == ref.shape == (nfr, N)
+    e, r = err_fs(y, ref, h.sum()), err_rel(y, ref)
+    log("  err_fs=%.3g err_rel=%.3g" % (e, r))
+    assert e <= TOL_FS and r <= TOL_REL
+
+
+@pytest.mark.parametrize("N,M", [(64, 4), (1024, 8), (4096, 3)])
+def test_pfb_split_invariance_bit_exact(N, M):
+    rf = _rf()
+    import torch
+    h = siggen.pfb_prototype(N, M, "hann")
+    n = N * (M + 40) + 5
+    iq = siggen.StreamSpec(13, siggen.pfb_small().stream.tones, 900.0).iq(0, n)
+    d = to_dev(iq)
+    log("pfb split N=%d M=%d" % (N, M))
+    whole = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, [n], torch)
+    rng = np.random.default_rng(N + M)
+    cuts = [0, 1, N - 1, N + 1, 3 * N, 0, N * M - 3, 7, N * 5 + 13]
+    sizes = list(cuts)
+    rest = n - sum(sizes)
+    while rest > 0:
+        s = int(min(rest, rng.integers(1, 4 * N)))
+        sizes.append(s)
+        rest -= s
+    part = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, sizes, torch)
+    assert part.shape == whole.shape
+    assert np.array_equal(part.view(np.uint64), whole.view(np.uint64))
+
+
+def test_pfb_state_resume_and_reset():
+    rf = _rf()
+    import torch
+    N, M = 256, 8
+    h = siggen.pfb_prototype(N, M, "kaiser")
+    n = N * 60 + 99
+    iq = siggen.StreamSpec(17, siggen.pfb_small().stream.tones, 500.0).iq(0, n)
+    d = to_dev(iq)
+    a = rf.Pfb(N, M, h, max_samples_per_call=n)
+    whole = run_pfb(a, d, [n], torch)
+    cut = N * 23 + 45
+    b = rf.Pfb(N, M, h, max_samples_per_call=n)
+    first = run_pfb(b, d[: 2 * cut], [cut], torch)
+    blob = b.get_state()
+    c = rf.Pfb(N, M, h, max_samples_per_call=n)
+    c.set_state(blob)
+    assert c.counters() == b.counters()
+    second = run_pfb(c, d[2 * cut:], [n - cut], torch)
+    got = np.concatenate([first, second])
+    assert np.array_equal(got.view(np.uint64), whole.view(np.uint64))
+    a.reset()
+    again = run_pfb(a, d, [n], torch)
+    assert np.array_equal(again.view(np.uint64), whole.view(np.uint64))
+    # a blob for another shape is refused and leaves the handle usable
+    other = rf.Pfb(128, 8, siggen.pfb_prototype(128, 8), max_samples_per_call=n)
+    with pytest.raises(rf.RfError):
+        other.set_state(blob)
+
+
+def test_pfb_edge_cases_and_errors():
+    rf = _rf()
+    import torch
+    N, M = 64, 4
+    h = siggen.pfb_prototype(N, M)
+    p = rf.Pfb(N, M, h, max_samples_per_call=4096)
+    dev = torch.device("cuda")
+    empty = torch.zeros(0, dtype=torch.int16, device=dev)
+    assert p.process(empty).shape == (0, N)
+    iq = siggen.StreamSpec(19, siggen.pfb_small().stream.tones, 1000.0).iq(0, 4096)
+    d = to_dev(iq)
+    # fewer than N*M samples: no frame yet, all retained
+    assert p.frames_for(N * M - 1) == 0
+    assert p.process(d[: 2 * (N * M - 1)]).shape == (0, N)
+    assert p.counters() == (N * M - 1, 0, N * M - 1)
+    # capacity too small: error, state unchanged
+    small = torch.empty((1, N), dtype=torch.complex64, device=dev)
+    with pytest.raises(rf.RfError) as ei:
+        p.process(d[2 * (N * M - 1): 2 * (N * M - 1 + 3 * N)], out=small)
+    assert ei.value.status == rf.RF_ECAPACITY
+    assert p.counters() == (N * M - 1, 0, N * M - 1)
+    # too many samples for this handle
+    big = torch.zeros(2 * 5000, dtype=torch.int16, device=dev)
+    with pytest.raises(rf.RfError) as ei:
+        p.process(big)
+    assert ei.value.status == rf.RF_EINVAL
+    y = p.process(d[2 * (N * M - 1):])
+    torch.cuda.synchronize()
+    ref = oracle.pfb(f32(h), N, M, iq=iq)
+    assert y.shape == ref.shape
+    assert err_fs(y.cpu().numpy(), ref, h.sum()) <= TOL_FS
+    # unaligned input pointer is rejected
+    with pytest.raises(rf.RfError):
+        p.process_ptr(d.data_ptr() + 2, 10, small.data_ptr(), 1, 0)
+
+
+def test_pfb_full_scale_tones():
+    """Bin-centred full-scale tone: channel amplitude ~ A * sum(h), GPU == oracle."""
+    rf = _rf()
+    import torch
+    N, M = 1024, 8
+    h = siggen.pfb_prototype(N, M, "kaiser", 9.0)
+    k0 = 317
+    tones = siggen.ToneSet(np.array([siggen.bin_word(k0, N)], dtype=np.uint64),
+                           np.array([8000.0]), np.array([0.4]))
+    n = N * 40
+    iq = siggen.StreamSpec(23, tones, 0.0).iq(0, n)
+    p = rf.Pfb(N, M, h, max_samples_per_call=n)
+    y = run_pfb(p, to_dev(iq), [n], torch)
+    ref = oracle.pfb(f32(h), N, M, iq=iq)
+    assert err_rel(y, ref) <= TOL_REL
+    assert np.allclose(np.abs(y[:, k0]), 8000.0, rtol=2e-4)
+
+
+def test_pfb_two_streams_are_ordered():
+    """Alternating HIP streams on one handle gives the single-stream result."""
+    rf = _rf()
+    import torch
+    N, M = 512, 4
+    h = siggen.pfb_prototype(N, M)
+    n = N * 64
+    iq = siggen.StreamSpec(29, siggen.pfb_small().stream.tones, 900.0).iq(0, n)
+    d = to_dev(iq)
+    whole = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, [n], torch)
+    p = rf.Pfb(N, M, h, max_samples_per_call=n)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    step = N * 7 + 3
+    torch.cuda.synchronize()
+    for i, pos in enumerate(range(0, n, step)):
+        m = min(step, n - pos)
+        s = s1 if i % 2 == 0 else s2
+        with torch.cuda.stream(s):
+            outs.append(p.process(d[2 * pos: 2 * (pos + m)], stream=s))
+    torch.cuda.synchronize()
+    got = torch.cat(outs).cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), whole.view(np.uint64))
+
+
+@pytest.mark.slow
+def test_pfb_production_full_size_sampled():
+    """N=1024, M=8, Kaiser(9): 2^28 samples in 16 buffers of 2^24 -> 262137 frames.
+
+    Inputs generated on the device (same recipe as the benchmark); sampled frames,
+    including every buffer boundary, are checked against the oracle.
+    """
+    rf = _rf()
+    import torch
+    w = siggen.pfb_production()
+    log("pfb production: generating 2^28 samples on the device")
+    d = siggen.iq_torch(w.stream, 0, w.nsamples)
+    torch.cuda.synchronize()
+    p = rf.Pfb(w.N, w.M, w.h, max_samples_per_call=w.buffer)
+    total = p.frames_for(w.nsamples)
+    out = torch.empty((262137, w.N), dtype=torch.complex64, device="cuda")
+    pos, f = 0, 0
+    bounds = []
+    while pos < w.nsamples:
+        got = p.process_ptr(d.data_ptr() + 4 * pos, w.buffer, out.data_ptr() + 8 * w.N * f,
+                            262137 - f, torch.cuda.current_stream().cuda_stream)
+        bounds.append(f)
+        f += got
+        pos += w.buffer
+    torch.cuda.synchronize()
+    assert total == 262137 and f == 262137
+    rng = np.random.default_rng(5)
+    frames = sorted(set([0, 1, 262136] + [b for b in bounds] + [b - 1 for b in bounds if b > 0]
+                        + list(rng.integers(0, 262137, 40))))
+    idx = torch.tensor(frames, device="cuda")
+    y = out.index_select(0, idx).cpu().numpy()
+    iq = d.cpu().numpy()
+    ref = oracle.pfb(f32(w.h), w.N, w.M, iq=iq, frames=frames)
+    e, r = err_fs(y, ref, w.h.sum()), err_rel(y, ref)
+    log("production sampled frames=%d err_fs=%.3g err_rel=%.3g" % (len(frames), e, r))
+    assert e <= TOL_FS and r <= TOL_REL
