@@ -1,0 +1,455 @@
+// pfb_kernels.hpp -- fused int16 unpack + polyphase FIR + FFT for gfx950.
+//
+// Critically sampled polyphase filter bank (paper Sec. III.A): frame p of an
+// N-channel bank with M taps per channel is
+//     v_p[n] = sum_m h[mN+n] x[pN+mN+n],   X_p[k] = sum_n v_p[n] exp(-2 pi i kn/N).
+// The paper folds with a cuBLAS product and transforms with batched cuFFT; here
+// one kernel reads every input sample once from HBM, keeps the FIR's sliding
+// window in registers and runs the FFT through LDS, writing only the spectra.
+//
+// Work decomposition (all compile-time in N):
+//  * A lane group (LG) of L = N/4 threads walks a contiguous run of frames.
+//    Thread c of an LG owns the four columns n = c + k*L (k = 0..3), holds their
+//    M taps and a window of M+3 blocks of input in registers, and produces four
+//    frames per phase.  Its four FIR outputs are exactly the inputs of one
+//    radix-4 butterfly of the first Stockham pass (stride N/4, no twiddles),
+//    which it computes before writing to LDS.
+//  * The remaining passes are radix-16 (radix 8/4/2 for the last one) Stockham
+//    passes: a team of N/16 threads owns one frame, every thread holds 16 points
+//    per pass.  The last pass writes the natural-order spectrum straight to HBM.
+//  * LDS holds the frames of one phase, indexed with one float2 of padding per
+//    64 entries (i + 4*(i>>6)) so the strided stores of the Ns = 4 pass hit
+//    distinct banks.  Pass twiddles are staged in LDS as [r][k] tables so that
+//    lanes with consecutive k read consecutive entries.
+//  * Work-groups whose every input block lies inside the new buffer (all but
+//    the first and last few) take a branch-free path with a per-run base
+//    pointer; the others resolve each block against the retained history.
+//  * Work-groups are remapped so that each of the 8 XCDs walks one contiguous
+//    part of the stream; neighbouring runs, which share M-1 blocks of input,
+//    then meet in the same L2.
+//
+// Variant bits (kernel template parameter V, chosen at launch):
+//   1: two LDS phase buffers, one work-group barrier per phase (N <= 1024);
+//   2: ordinary (write-back) stores instead of non-temporal stores.
+#pragma once
+#include "fft_device.hpp"
+#include "rf_internal.hpp"
+
+namespace rfk {
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+template <int N>
+struct PfbPlan {
+    static constexpr int L = N / 4;                  // threads per lane group
+    static constexpr int WG = L > 256 ? L : 256;     // threads per work-group
+    static constexpr int NLG = WG / L;               // lane groups per work-group
+    static constexpr int FB = NLG * 4;               // frames per phase buffer
+    static constexpr int NT = N / 16;                // FFT team size (threads)
+    static constexpr int LDS = FB * N + 4 * ((FB * N) >> 6);
+    static constexpr bool LG_IN_WAVE = L <= 64;      // FIR and FFT of an LG stay in one wave
+    static constexpr bool TEAM_IN_WAVE = NT <= 64;
+};
+
+__host__ __device__ constexpr int pass_radix(int N, int NS) { return (N / NS) >= 16 ? 16 : (N / NS); }
+
+// Offset (in float pairs) of the twiddle table of the pass with stride NS.
+__host__ __device__ constexpr int tw_offset(int N, int NS)
+{
+    int off = 0;
+    for (int ns = 4; ns < NS;) {
+        int R = pass_radix(N, ns);
+        off += ns * R;
+        ns *= R;
+    }
+    return off;
+}
+
+// Twiddles of R = 16 passes, and of every pass when N <= 2048, are staged in
+// LDS; otherwise (the radix-4 last pass of N = 4096) W^k is read once and its
+// powers formed by multiplication.
+template <int N, int NS>
+struct TwPlace {
+    static constexpr int R = pass_radix(N, NS);
+    static constexpr bool IN_LDS = (R == 16) || (N <= 2048);
+};
+
+template <int N>
+__host__ __device__ constexpr int lds_tw_count()
+{
+    int n = 0;
+    for (int ns = 4; ns < N;) {
+        int R = pass_radix(N, ns);
+        if (R == 16 || N <= 2048) n += ns * R;
+        ns *= R;
+    }
+    return n > 0 ? n : 1;
+}
+
+__device__ __forceinline__ int lpad(int i) { return i + 4 * (i >> 6); }
+
+__device__ __forceinline__ void wave_fence()
+{
+    // LDS accesses of one wave complete in issue order; keep the compiler from
+    // moving them across this point.
+    __asm__ __volatile__("" ::: "memory");
+}
+
+template <bool CROSS_WAVE>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (CROSS_WAVE)
+        __syncthreads();
+    else
+        wave_fence();
+}
+
+__device__ __forceinline__ uint32_t vload(const VStream &vs, int64_t v)
+{
+    return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
+}
+
+__device__ __forceinline__ cf unpack(uint32_t w)
+{
+    return {(float)(int16_t)(w & 0xffffu), (float)(int16_t)(w >> 16)};
+}
+
+// Load four columns c + k*L of virtual block b (samples [bN, bN+N)), resolving
+// each against history, new input and end of data.
+template <int N>
+__device__ __forceinline__ void load_block(const VStream &vs, int64_t vlen, int64_t b, int c,
+                                           uint32_t (&w)[4])
+{
+    constexpr int L = N / 4;
+    const int64_t base = b * N;
+    if (base + N <= vlen) {
+        if (base >= vs.H) {
+            const uint32_t *p = vs.in + (base - vs.H) + c;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = p[k * L];
+        } else if (base + N <= vs.H) {
+            const uint32_t *p = vs.hist + base + c;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = p[k * L];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = vload(vs, base + c + k * L);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int64_t v = base + c + k * L;
+            w[k] = v < vlen ? vload(vs, v) : 0u;
+        }
+    }
+}
+
+// One Stockham pass of radix R and stride NS over the frame at `fb` (LDS,
+// unpadded frame base).  Thread `tl` of the frame's team handles butterflies
+// j = tl + b*NT.  The last pass stores to `outf` (global, frame base).
+template <int N, int R, int NS, bool LAST, bool NT_STORE>
+__device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
+                                         const cf *__restrict__ twg, float *__restrict__ outf,
+                                         bool valid)
+{
+    constexpr int NT = PfbPlan<N>::NT;
+    constexpr int NB = N / R;
+    constexpr int BPT = NB / NT;
+    constexpr bool XW = !PfbPlan<N>::TEAM_IN_WAVE;
+    constexpr int TOFF = tw_offset(N, NS);
+    static_assert(BPT * NT == NB, "team does not tile the pass");
+    cf v[BPT][R];
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int j = tl + b * NT;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b][r] = lds[lpad(fb + j + r * NB)];
+    }
+    group_sync<XW>();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int j = tl + b * NT;
+        const int k = j % NS;
+        if constexpr (NS > 1) {
+            if constexpr (TwPlace<N, NS>::IN_LDS) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], twl[TOFF + r * NS + k]);
+            } else {
+                const cf w1 = twg[TOFF + NS + k];
+                cf w = w1;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    v[b][r] = cmul(v[b][r], w);
+                    if (r + 1 < R) w = cmul(w, w1);
+                }
+            }
+        }
+        dft<R>(v[b]);
+        const int idxD = (j / NS) * NS * R + k;
+        if constexpr (LAST) {
+            if (valid) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    f2v o = {v[b][r].x, v[b][r].y};
+                    f2v *dst = (f2v *)(outf + 2 * (idxD + r * NS));
+                    if constexpr (NT_STORE)
+                        __builtin_nontemporal_store(o, dst);
+                    else
+                        *dst = o;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lpad(fb + idxD + r * NS)] = v[b][r];
+        }
+    }
+    if constexpr (!LAST) group_sync<XW>();
+}
+
+template <int N, int NS, bool NT_STORE>
+__device__ __forceinline__ void fft_passes(cf *lds, int fb, int tl, const cf *twl,
+                                           const cf *__restrict__ twg, float *__restrict__ outf,
+                                           bool valid)
+{
+    if constexpr (NS < N) {
+        constexpr int R = pass_radix(N, NS);
+        fft_pass<N, R, NS, NS * R == N, NT_STORE>(lds, fb, tl, twl, twg, outf, valid);
+        fft_passes<N, NS * R, NT_STORE>(lds, fb, tl, twl, twg, outf, valid);
+    }
+}
+
+// Window element: unpacked FP32 pair, or the raw packed word for large M
+// (fewer registers, one conversion per use).
+template <bool PACKED>
+struct WinT;
+template <>
+struct WinT<false> {
+    cf v;
+    __device__ __forceinline__ void set(uint32_t w) { v = unpack(w); }
+    __device__ __forceinline__ cf get() const { return v; }
+};
+template <>
+struct WinT<true> {
+    uint32_t w;
+    __device__ __forceinline__ void set(uint32_t x) { w = x; }
+    __device__ __forceinline__ cf get() const { return unpack(w); }
+};
+
+template <int N, int M>
+struct FirState {
+    static constexpr bool PACKED = (M > 8) || (N >= 4096);
+    static constexpr int W = M + 3;   // window blocks fp .. fp+M+2
+    float hr[M][4];
+    WinT<PACKED> xw[W][4];
+};
+
+// FIR of the phase's four frames, first radix-4 pass, store to LDS.
+template <int N, int M>
+__device__ __forceinline__ void fir_phase(const FirState<N, M> &st, cf *lds, int g, int c)
+{
+#pragma unroll
+    for (int qf = 0; qf < 4; ++qf) {
+        cf v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cf s = {0.f, 0.f};
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const cf x = st.xw[qf + m][k].get();
+                s.x = __builtin_fmaf(st.hr[m][k], x.x, s.x);
+                s.y = __builtin_fmaf(st.hr[m][k], x.y, s.y);
+            }
+            v[k] = s;
+        }
+        dft4(v[0], v[1], v[2], v[3]);
+        const int fb = (g * 4 + qf) * N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lds[lpad(fb + 4 * c + r)] = v[r];
+    }
+}
+
+template <int N, int M>
+__device__ __forceinline__ void shift_window(FirState<N, M> &st, const uint32_t (&pre)[4][4])
+{
+    constexpr int W = FirState<N, M>::W;
+#pragma unroll
+    for (int i = 0; i + 4 < W; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) st.xw[i][k] = st.xw[i + 4][k];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) st.xw[W - 4 + i][k].set(pre[i][k]);
+}
+
+template <int N, int V>
+struct PfbVariant {
+    static constexpr bool DBUF = (V & 1) && N <= 1024 && !PfbPlan<N>::LG_IN_WAVE;
+    static constexpr bool NT_STORE = !(V & 2);
+    static constexpr int NBUF = DBUF ? 2 : 1;
+};
+
+template <int N, int M, int V>
+__global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_fir_fft(PfbLaunch a)
+{
+    using P = PfbPlan<N>;
+    using VV = PfbVariant<N, V>;
+    constexpr int L = P::L;
+    constexpr int W = FirState<N, M>::W;
+    constexpr int TWL = lds_tw_count<N>();
+    // one barrier per phase when double buffered, else two
+    constexpr bool SYNC2 = !P::LG_IN_WAVE && !VV::DBUF;
+    __shared__ cf lds_all[VV::NBUF * P::LDS];
+    __shared__ cf twl[TWL];
+
+    const int tid = threadIdx.x;
+    const cf *twg = reinterpret_cast<const cf *>(a.tw);
+    for (int i = tid; i < TWL; i += P::WG) twl[i] = twg[i];
+
+    // XCD-aware work-group order: blocks are dealt round-robin to the 8 XCDs,
+    // so give XCD x the contiguous logical range [x*q + min(x,r), ...).
+    const int G = gridDim.x, bid = blockIdx.x;
+    const int xq = G >> 3, xr = G & 7, xcd = bid & 7;
+    const int lwg = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
+
+    const VStream vs = a.vs;
+    const int64_t vlen = vs.H + vs.n;
+    const int64_t F = a.F;
+    const int RL = a.run_len;
+    const int nph = RL >> 2;
+
+    const int g = tid / L;
+    const int c = tid - g * L;
+    const int64_t f0 = ((int64_t)lwg * P::NLG + g) * RL;
+
+    // Every block this work-group touches lies inside the new input: no
+    // history, no tail, every frame valid.  Uniform per work-group.
+    const int64_t wg_first = (int64_t)lwg * P::NLG * RL;
+    const int64_t wg_last = wg_first + (int64_t)P::NLG * RL + M - 2;
+    const bool fast = wg_first * N >= vs.H && (wg_last + 1) * N <= vlen;
+
+    FirState<N, M> st;
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) st.hr[m][k] = a.taps[m * N + c + k * L];
+
+    // FFT team of this thread (may belong to another lane group for N >= 512)
+    const int slot = tid / P::NT;
+    const int tl = tid - slot * P::NT;
+    const int lg2 = slot >> 2, q2 = slot & 3;
+    const int64_t f0t = ((int64_t)lwg * P::NLG + lg2) * RL;
+    const int64_t f1t = (f0t + RL < F) ? f0t + RL : F;
+    __syncthreads();   // twiddle tables staged
+
+    if (fast) {
+        // block b of this lane group starts at in + (f0 + b)*N - H
+        const uint32_t *base = vs.in + (f0 * N - vs.H) + c;
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) st.xw[i][k].set(base[i * N + k * L]);
+        for (int ph = 0; ph < nph; ++ph) {
+            cf *lds = lds_all + (VV::DBUF ? (ph & 1) * P::LDS : 0);
+            uint32_t pre[4][4];
+            const bool more = ph + 1 < nph;
+            if (more) {
+                const uint32_t *p = base + (int64_t)(4 * ph + W) * N;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) pre[i][k] = p[i * N + k * L];
+            }
+            fir_phase<N, M>(st, lds, g, c);
+            group_sync<!P::LG_IN_WAVE>();
+            fft_passes<N, 4, VV::NT_STORE>(lds, slot * N, tl, twl, twg,
+                                           a.out + 2 * (f0t + 4 * ph + q2) * (int64_t)N, true);
+            if constexpr (SYNC2) group_sync<true>();
+            else wave_fence();
+            if (more) shift_window<N, M>(st, pre);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            uint32_t w[4];
+            load_block<N>(vs, vlen, f0 + i, c, w);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) st.xw[i][k].set(w[k]);
+        }
+        for (int ph = 0; ph < nph; ++ph) {
+            cf *lds = lds_all + (VV::DBUF ? (ph & 1) * P::LDS : 0);
+            const int64_t fp = f0 + 4 * ph;
+            uint32_t pre[4][4];
+            const bool more = (ph + 1 < nph) && (fp + 4 < F);
+            if (more) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) load_block<N>(vs, vlen, fp + W + i, c, pre[i]);
+            }
+            if (fp < F) fir_phase<N, M>(st, lds, g, c);
+            group_sync<!P::LG_IN_WAVE>();
+            {
+                const int64_t f = f0t + 4 * ph + q2;
+                const bool valid = f < f1t;
+                fft_passes<N, 4, VV::NT_STORE>(lds, slot * N, tl, twl, twg,
+                                               a.out + 2 * (valid ? f : 0) * (int64_t)N, valid);
+            }
+            if constexpr (SYNC2) group_sync<true>();
+            else wave_fence();
+            if (more) shift_window<N, M>(st, pre);
+        }
+    }
+
+    // retained history for the next call (sources are read-only this call)
+    for (int64_t i = (int64_t)bid * P::WG + tid; i < a.keep_len; i += (int64_t)G * P::WG)
+        a.hist_out[i] = vload(vs, a.keep_from + i);
+}
+
+template <int N, int M, int V>
+hipError_t launch_pfb_nmv(const PfbLaunch &a, hipStream_t s)
+{
+    using P = PfbPlan<N>;
+    const int64_t runs = (a.F + a.run_len - 1) / a.run_len;
+    int64_t wgs = (runs + P::NLG - 1) / P::NLG;
+    if (wgs < 1) wgs = 1;
+    if (wgs > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((pfb_fir_fft<N, M, V>), dim3((unsigned)wgs), dim3(P::WG), 0, s, a);
+    return hipGetLastError();
+}
+
+// Dispatch over M (1..16) for a fixed N with the default variant.
+template <int N, int V>
+hipError_t launch_pfb_nv(const PfbLaunch &a, hipStream_t s)
+{
+    switch (a.M) {
+    case 1: return launch_pfb_nmv<N, 1, V>(a, s);
+    case 2: return launch_pfb_nmv<N, 2, V>(a, s);
+    case 3: return launch_pfb_nmv<N, 3, V>(a, s);
+    case 4: return launch_pfb_nmv<N, 4, V>(a, s);
+    case 5: return launch_pfb_nmv<N, 5, V>(a, s);
+    case 6: return launch_pfb_nmv<N, 6, V>(a, s);
+    case 7: return launch_pfb_nmv<N, 7, V>(a, s);
+    case 8: return launch_pfb_nmv<N, 8, V>(a, s);
+    case 9: return launch_pfb_nmv<N, 9, V>(a, s);
+    case 10: return launch_pfb_nmv<N, 10, V>(a, s);
+    case 11: return launch_pfb_nmv<N, 11, V>(a, s);
+    case 12: return launch_pfb_nmv<N, 12, V>(a, s);
+    case 13: return launch_pfb_nmv<N, 13, V>(a, s);
+    case 14: return launch_pfb_nmv<N, 14, V>(a, s);
+    case 15: return launch_pfb_nmv<N, 15, V>(a, s);
+    case 16: return launch_pfb_nmv<N, 16, V>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Per-N entry points, each defined in its own translation unit.
+hipError_t launch_pfb_n16(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n32(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n64(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n128(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n256(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n512(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n2048(const PfbLaunch &a, hipStream_t s);
+hipError_t launch_pfb_n4096(const PfbLaunch &a, hipStream_t s);
+
+}  // namespace rfk

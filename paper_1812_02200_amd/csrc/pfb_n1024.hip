@@ -1,0 +1,20 @@
+// Instantiations of the fused PFB kernel for N = 1024 (M = 1..16), plus the
+// tunable variants of the M = 8 kernel (double-buffered LDS, store type).
+#include "pfb_kernels.hpp"
+
+namespace rfk {
+
+hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s)
+{
+    if (a.M == 8) {
+        switch (a.variant) {
+        case 1: return launch_pfb_nmv<1024, 8, 1>(a, s);
+        case 2: return launch_pfb_nmv<1024, 8, 2>(a, s);
+        case 3: return launch_pfb_nmv<1024, 8, 3>(a, s);
+        default: break;
+        }
+    }
+    return launch_pfb_nv<1024, 0>(a, s);
+}
+
+}  // namespace rfk

@@ -1,0 +1,8 @@
+// Instantiations of the fused PFB kernel for N = 2048 (M = 1..16).
+#include "pfb_kernels.hpp"
+
+namespace rfk {
+
+hipError_t launch_pfb_n2048(const PfbLaunch &a, hipStream_t s) { return launch_pfb_nv<2048, 0>(a, s); }
+
+}  // namespace rfk

@@ -1,0 +1,8 @@
+// Instantiations of the fused PFB kernel for N = 4096 (M = 1..16).
+#include "pfb_kernels.hpp"
+
+namespace rfk {
+
+hipError_t launch_pfb_n4096(const PfbLaunch &a, hipStream_t s) { return launch_pfb_nv<4096, 0>(a, s); }
+
+}  // namespace rfk

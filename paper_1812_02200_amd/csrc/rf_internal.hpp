@@ -26,6 +26,7 @@ struct PfbLaunch {
     int64_t F;              // frames to emit
     int32_t run_len;        // frames per lane-group run (multiple of 4)
     int32_t N, M;
+    int32_t variant;        // kernel variant bits (0: default)
 };
 
 struct DdcLaunch {

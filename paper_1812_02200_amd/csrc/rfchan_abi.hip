@@ -136,6 +136,7 @@ struct rf_pfb {
     uint64_t frames = 0;   // frames emitted
     int64_t H = 0;         // retained samples (virtual stream starts at frames*N)
     int run_len = 0;       // 0: heuristic
+    int variant = 0;       // kernel variant bits
     StreamOrder order;
 };
 
@@ -247,6 +248,8 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         int v = atoi(rl);
         if (v >= 4 && v % 4 == 0) p->run_len = v;
     }
+    const char *vr = getenv("RFCHAN_PFB_VARIANT");
+    if (vr) p->variant = atoi(vr);
     *out = p;
     return RF_OK;
 }
@@ -297,6 +300,7 @@ int pfb_process(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out
     a.run_len = p->run_len > 0 ? p->run_len : rfk::pfb_default_run_len(p->N, p->M, (int64_t)F);
     a.N = p->N;
     a.M = p->M;
+    a.variant = p->variant;
     HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
 
     p->order.after(s);
