@@ -101,21 +101,20 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
 
 
 def cpu_pfb(oracle, w, d, budget_s):
-    """The FP64 oracle on a bounded sample of the same stream (host cores)."""
-    nf = 256
-    iq = d[: 2 * (nf + w.M) * w.N].cpu().numpy()
-    t0 = time.perf_counter()
-    oracle.pfb(w.h, w.N, w.M, iq=iq, frames=np.arange(nf))
-    t = time.perf_counter() - t0
-    nf = int(min(16384, max(nf, nf * budget_s / max(t, 1e-6))))
-    iq = d[: 2 * (nf + w.M) * w.N].cpu().numpy()
-    t0 = time.perf_counter()
-    oracle.pfb(w.h, w.N, w.M, iq=iq, frames=np.arange(nf))
-    t = time.perf_counter() - t0
-    return {"value": nf * w.N / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
+    """The FP64 oracle on the same stream (host cores), repeated up to ~budget_s."""
+    nf = oracle.pfb_nframes(w.nsamples, w.N, w.M)
+    iq = d.cpu().numpy()
+    frames = np.arange(nf)
+    reps, t = 0, 0.0
+    while t < budget_s and reps < 64:
+        t0 = time.perf_counter()
+        oracle.pfb(w.h, w.N, w.M, iq=iq, frames=frames)
+        t += time.perf_counter() - t0
+        reps += 1
+    return {"value": reps * nf * w.N / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": t,
-            "sample": "%d frames (%d samples) of the N=1024 M=8 stream, FP64, OpenMP over frames"
-                      % (nf, nf * w.N)}
+            "sample": "all %d frames of the 2^28-sample N=1024 M=8 stream x %d passes, FP64, "
+                      "OpenMP over frames" % (nf, reps)}
 
 
 # ------------------------------------------------------------------ DDC
@@ -170,6 +169,7 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
 
 
 def cpu_ddc(oracle, w, d, budget_s):
+    """The FP64 oracle on the first outputs of every tone, sized to ~budget_s of CPU work."""
     iq = d[: 2 * (w.buffer)].cpu().numpy()
     nout = oracle.ddc_noutputs(w.buffer, w.h.size, w.D)
     ntones = w.words.size
@@ -181,13 +181,14 @@ def cpu_ddc(oracle, w, d, budget_s):
         oracle.ddc_points(w.words, w.phase0, w.h, w.D, ti, oi, iq=iq)
         return time.perf_counter() - t0
 
-    t = run(1)
-    k = int(min(nout, max(1, budget_s / max(t, 1e-6))))
+    k = 8
+    t = run(k)
+    k = int(min(nout, max(k, k * budget_s / max(t, 1e-6))))
     t = run(k)
     # k outputs of every tone cover k*D input samples of the 1000-tone bank
     return {"value": k * w.D / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": t,
-            "sample": "%d outputs x %d tones (%d input samples), FP64, OpenMP over points"
+            "sample": "first %d outputs of all %d tones (%d input samples), FP64, OpenMP over points"
                       % (k, ntones, k * w.D)}
 
 
