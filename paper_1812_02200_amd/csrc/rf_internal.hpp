@@ -54,6 +54,12 @@ int pfb_twiddle_count(int N);
 void pfb_twiddle_fill(int N, float *tw);
 
 hipError_t launch_pfb(const PfbLaunch &a, hipStream_t s);
+
+// DFT on MFMA with hi/lo half-precision operands (N = 256 only).
+enum { RF_PREC_F16 = 1, RF_PREC_BF16 = 2 };
+hipError_t launch_pfb_mfma(const PfbLaunch &a, int prec, hipStream_t s);
+int pfb_mfma_table_floats();
+void pfb_mfma_table_fill(float *t);
 // Frames per run and launch geometry the PFB launcher will use.
 int pfb_default_run_len(int N, int M, int64_t F);
 

@@ -204,8 +204,8 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         return fail(RF_EINVAL, "pfb_create: max_samples_per_call out of range");
     if (dft_mode != RF_DFT_FFT_F32 && dft_mode != RF_DFT_MFMA_F16X2 && dft_mode != RF_DFT_MFMA_BF16X2)
         return fail(RF_EINVAL, "pfb_create: unknown dft_mode %d", dft_mode);
-    if (dft_mode != RF_DFT_FFT_F32)
-        return fail(RF_EUNSUPPORTED, "pfb_create: MFMA DFT modes are not built in this version");
+    if (dft_mode != RF_DFT_FFT_F32 && nchan != 256)
+        return fail(RF_EUNSUPPORTED, "pfb_create: the MFMA DFT modes support nchan=256 only");
     for (int i = 0; i < nchan * ntaps; ++i)
         if (!isfinite(proto[i])) return fail(RF_EINVAL, "pfb_create: proto[%d] is not finite", i);
 
@@ -222,13 +222,18 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         return hip_fail(e, "hipGetDevice");
     }
     const size_t span = (size_t)nchan * ntaps;
-    const int ntw = rfk::pfb_twiddle_count(nchan);
+    // FFT: pass twiddle tables (float pairs); MFMA: DFT16 block matrix + W256 twiddles
+    const int ntw = dft_mode == RF_DFT_FFT_F32 ? rfk::pfb_twiddle_count(nchan)
+                                               : (rfk::pfb_mfma_table_floats() + 1) / 2;
     float *tw = (float *)malloc(sizeof(float) * 2 * ntw);
     if (!tw) {
         pfb_free(p);
         return fail(RF_ENOMEM, "pfb_create: host allocation");
     }
-    rfk::pfb_twiddle_fill(nchan, tw);
+    if (dft_mode == RF_DFT_FFT_F32)
+        rfk::pfb_twiddle_fill(nchan, tw);
+    else
+        rfk::pfb_mfma_table_fill(tw);
     if ((rc = dev_alloc(&p->d_taps, span, "taps")) || (rc = dev_alloc(&p->d_tw, 2 * (size_t)ntw, "twiddles")) ||
         (rc = dev_alloc(&p->d_hist[0], span, "history")) || (rc = dev_alloc(&p->d_hist[1], span, "history"))) {
         free(tw);
@@ -301,7 +306,11 @@ int pfb_process(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out
     a.N = p->N;
     a.M = p->M;
     a.variant = p->variant;
-    HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
+    if (p->mode == RF_DFT_FFT_F32)
+        HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
+    else
+        HIP_TRY(rfk::launch_pfb_mfma(a, p->mode == RF_DFT_MFMA_BF16X2 ? rfk::RF_PREC_BF16 : rfk::RF_PREC_F16, s),
+                "pfb mfma kernel launch");
 
     p->order.after(s);
     p->cur ^= 1;
