@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "pfb", "ddc"])
+    ap.add_argument("--workload", default="all", choices=["all", "pfb", "ddc", "precision"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget per oracle baseline sample")
@@ -168,6 +168,74 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     }, (w, d)
 
 
+# ------------------------------------------------------------- precision
+
+MFMA_PEAK_TF = 2500.0          # MI355X dense FP16/BF16 MFMA, published
+
+
+def bench_precision(rf, torch, siggen, oracle, steps, warmup):
+    """N=256, M=8, Kaiser(9), 2^22 frames: FP32 FFT vs DFT on FP16 / BF16 MFMA (hi/lo)."""
+    w = siggen.pfb_precision()
+    nf = 1 << 22
+    log("precision: generating %d samples on the device" % w.nsamples)
+    d = siggen.iq_torch(w.stream, 0, w.nsamples)
+    out = torch.empty((nf, w.N), dtype=torch.complex64, device="cuda")
+    s = torch.cuda.current_stream()
+    sh = s.cuda_stream
+    # reference frames: 8 blocks of 128 frames spread over the stream
+    rng = np.random.default_rng(4)
+    starts = sorted(rng.choice(nf // 128, size=8, replace=False) * 128)
+    refs = []
+    span = w.N * w.M
+    for f0 in starts:
+        iq = d[2 * f0 * w.N: 2 * ((f0 + 127) * w.N + span)].cpu().numpy()
+        refs.append(oracle.pfb(np.asarray(w.h, np.float32).astype(np.float64), w.N, w.M, iq=iq))
+    res = {"config": {"workload": w.name, "N": w.N, "M": w.M, "frames": nf,
+                      "samples": w.nsamples}}
+    for name, mode in (("fft_f32", 0), ("mfma_f16x2", 1), ("mfma_bf16x2", 2)):
+        p = rf.Pfb(w.N, w.M, w.h, dft_mode=mode, max_samples_per_call=w.nsamples)
+
+        def once():
+            p.reset()
+            got = p.process_ptr(d.data_ptr(), w.nsamples, out.data_ptr(), nf, sh)
+            assert got == nf
+
+        for _ in range(warmup):
+            once()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for _ in range(steps):
+            e0.record(s)
+            p.process_ptr(d.data_ptr(), w.nsamples, out.data_ptr(), nf, sh)
+            e1.record(s)
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+            p.reset()
+        ms = tot / steps
+        once()
+        torch.cuda.synchronize()
+        snr = []
+        for f0, ref in zip(starts, refs):
+            y = out[f0: f0 + 128].cpu().numpy().astype(np.complex128)
+            snr.append((np.sum(np.abs(ref) ** 2, 0), np.sum(np.abs(y - ref) ** 2, 0)))
+        num = sum(a for a, _ in snr)
+        den = sum(b for _, b in snr)
+        ch = 10 * np.log10(num / np.maximum(den, 1e-300))
+        r = {"ms": ms, "msamples_per_s": w.nsamples / (ms / 1e3) / 1e6,
+             "hbm_frac": 12.0 * w.nsamples / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+             "channel_snr_db": {"min": float(ch.min()), "median": float(np.median(ch)),
+                                "max": float(ch.max())}}
+        if mode:
+            flop = 2.0 * 2 * 3 * 32 * 32 * 16 * nf    # 2 GEMM stages x 3 hi/lo terms per frame
+            r["mfma_tflops"] = flop / (ms / 1e3) / 1e12
+            r["mfma_frac"] = r["mfma_tflops"] / MFMA_PEAK_TF
+        res[name] = r
+        log("precision %s: %.3f ms, SNR min %.1f dB" % (name, ms, ch.min()))
+        p.close()
+    return res
+
+
 def cpu_ddc(oracle, w, d, budget_s):
     """The FP64 oracle on the first outputs of every tone, sized to ~budget_s of CPU work."""
     iq = d[: 2 * (w.buffer)].cpu().numpy()
@@ -226,6 +294,9 @@ def main():
             rec["config"] = r["config"]
             rec["roofline"] = r["roofline"]
         log("ddc: %.0f Msamples/s, %.1f us/launch" % (r["value"], r["kernel_us"]))
+    if a.workload in ("all", "precision"):
+        import oracle
+        rec["precision"] = bench_precision(rf, torch, siggen, oracle, max(1, min(a.steps, 5)), 1)
     if not a.no_cpu_baseline:
         import oracle
         if "pfb" in keep:

@@ -67,9 +67,9 @@ int rf_version(void);
 typedef struct rf_pfb *rf_pfb_t;
 
 /* DFT stage implementations. */
-#define RF_DFT_FFT_F32 0      /* FP32 FFT (radix-4/16 Stockham in LDS)        */
-#define RF_DFT_MFMA_F16X2 1   /* DFT as a GEMM on FP16 MFMA, hi/lo split, N<=256 */
-#define RF_DFT_MFMA_BF16X2 2  /* DFT as a GEMM on BF16 MFMA, hi/lo split, N<=256 */
+#define RF_DFT_FFT_F32 0      /* FP32 FFT (radix-4/16 Stockham in LDS)                  */
+#define RF_DFT_MFMA_F16X2 1   /* DFT as GEMMs on FP16 MFMA, hi/lo split operands, N=256 */
+#define RF_DFT_MFMA_BF16X2 2  /* DFT as GEMMs on BF16 MFMA, hi/lo split operands, N=256 */
 
 /* Create a channelizer on the current HIP device.
  *   out       receives the handle.
@@ -77,7 +77,7 @@ typedef struct rf_pfb *rf_pfb_t;
  *   ntaps     M: 1 <= M <= 16.
  *   proto     host array of N*M FP32 prototype taps h[0..N*M); copied, the
  *             caller may free it on return.
- *   dft_mode  one of RF_DFT_*; the MFMA modes need N <= 256
+ *   dft_mode  one of RF_DFT_*; the MFMA modes need N == 256
  *             (RF_EUNSUPPORTED otherwise).
  *   max_samples_per_call  largest nsamples a single pfb_process will accept
  *             (>= 1).  Bounds the work of one call; no memory scales with it.
@@ -181,6 +181,102 @@ int ddc_get_state(rf_ddc_t ddc, void *blob, size_t *size);
 int ddc_set_state(rf_ddc_t ddc, const void *blob, size_t size);
 int ddc_reset(rf_ddc_t ddc);
 int ddc_destroy(rf_ddc_t ddc);
+
+/* ============================================================ Serving
+ *
+ * A server multiplexes many readout streams onto one GPU, the way the paper's
+ * host threads hand pre-allocated buffers to the GPU signal-processing thread
+ * through lock-free queues (Sec. III, Fig. 2).  Each stream is a PFB and/or a
+ * DDC bank with its own filter history and oscillator phase kept on the
+ * device.  Requests (one buffer of a stream each) are queued as they arrive; a
+ * scheduler thread continuously forms batches from the oldest pending buffer
+ * of every stream that has a free output slot, and runs each batch as grouped
+ * kernels (one per channel/tap class plus one for all DDC banks) whose
+ * work-groups stride over the buffers of all streams in the batch.  Requests
+ * that arrive while a batch is on the GPU join the next one.  Streams are
+ * admitted by their device-memory footprint against a budget.
+ *
+ * Input buffers are device pointers owned by the caller, kept alive until the
+ * request completes.  Results stay in the stream's output slot until the
+ * caller releases it (rfs_release).  All calls are thread-safe.
+ */
+typedef struct rfs_server *rfs_t;
+
+#define RFS_PFB 1
+#define RFS_DDC 2
+
+#define RFS_MODE_SEQUENTIAL 0 /* one plain kernel per request, in arrival order (baseline) */
+#define RFS_MODE_BATCHED 1    /* grouped persistent kernels, launched directly per batch */
+#define RFS_MODE_GRAPH 2      /* grouped persistent kernels, replayed from captured hipGraphs */
+
+typedef struct {
+    int32_t kinds;            /* RFS_PFB and/or RFS_DDC */
+    int32_t nchan, ntaps;     /* PFB: N (power of two, 16..4096), M (1..16) */
+    const float *proto;       /* PFB: host, N*M taps (copied) */
+    int32_t ntones;           /* DDC: 1..65536 */
+    const uint64_t *phase_inc;/* DDC: host, tuning words (copied) */
+    const uint64_t *phase0;   /* DDC: host or NULL */
+    int32_t lpf_taps;         /* DDC: T (1..4096) */
+    const float *lpf;         /* DDC: host, T taps (copied) */
+    int32_t decim;            /* DDC: D */
+    uint64_t max_buffer;      /* largest nsamples of one request */
+    int32_t out_slots;        /* output slots of the stream, >= 1 */
+} rfs_stream_desc;
+
+typedef struct {
+    int32_t stream;
+    int32_t slot;             /* output slot holding the results */
+    uint64_t tag;             /* caller's tag from rfs_submit */
+    uint64_t nsamples;
+    int32_t status;           /* RF_OK, or the error of this request */
+    int32_t pad;
+    uint64_t pfb_frames;      /* frames written (PFB streams) */
+    const float *pfb_out;     /* device: pfb_frames x N complex64 */
+    uint64_t ddc_outputs;     /* outputs per tone written (DDC streams) */
+    uint64_t ddc_ld;          /* row stride of ddc_out in complex values */
+    const float *ddc_out;     /* device: ntones x ddc_ld complex64, tone-major */
+    double t_submit, t_launch, t_done;  /* seconds on rfs_now()'s clock */
+} rfs_completion;
+
+typedef struct {
+    uint64_t requests, batches, samples;
+    uint64_t bytes_admitted, bytes_budget;
+    int32_t streams_open, pad;
+    double gpu_busy_seconds;  /* sum of batch durations (host-observed) */
+} rfs_stats;
+
+/* Create a server on the current device with a device-memory budget for
+ * stream state and output slots, a scheduling mode (RFS_MODE_*) and a limit on
+ * open streams.  Starts the scheduler thread. */
+int rfs_create(rfs_t *out, uint64_t hbm_budget_bytes, int32_t mode, int32_t max_streams);
+
+/* Device bytes a stream with this description occupies (state + output slots). */
+uint64_t rfs_stream_footprint(const rfs_stream_desc *desc);
+
+/* Open a stream; *id receives its number.  RF_EAGAIN when its footprint does
+ * not fit in the remaining budget or max_streams are open (retry after others
+ * close); RF_EINVAL for a bad description. */
+int rfs_open_stream(rfs_t s, const rfs_stream_desc *desc, int32_t *id);
+
+/* Queue the next buffer of stream `id` (device pointer, nsamples <= max_buffer). */
+int rfs_submit(rfs_t s, int32_t id, const int16_t *iq_dev, uint64_t nsamples, uint64_t tag);
+
+/* Collect up to `max` completions, waiting up to timeout_us (0: do not wait). */
+int rfs_poll(rfs_t s, rfs_completion *out, int32_t max, int32_t *count, int32_t timeout_us);
+
+/* Return an output slot of stream `id` to the server after reading it. */
+int rfs_release(rfs_t s, int32_t id, int32_t slot);
+
+/* Close a stream with no queued or running requests (RF_EAGAIN otherwise). */
+int rfs_close_stream(rfs_t s, int32_t id);
+
+int rfs_get_stats(rfs_t s, rfs_stats *st);
+
+/* The server's monotonic clock in seconds (for arrival timestamps). */
+double rfs_now(void);
+
+/* Stop the scheduler, wait for the GPU, free everything (NULL is accepted). */
+int rfs_destroy(rfs_t s);
 
 #ifdef __cplusplus
 }

@@ -32,6 +32,37 @@ _I32 = ctypes.c_int32
 _U64 = ctypes.c_uint64
 _SZ = ctypes.c_size_t
 
+RFS_PFB = 1
+RFS_DDC = 2
+RFS_MODE_SEQUENTIAL = 0
+RFS_MODE_BATCHED = 1
+RFS_MODE_GRAPH = 2
+
+
+class StreamDesc(ctypes.Structure):
+    _fields_ = [("kinds", ctypes.c_int32), ("nchan", ctypes.c_int32), ("ntaps", ctypes.c_int32),
+                ("proto", ctypes.c_void_p), ("ntones", ctypes.c_int32),
+                ("phase_inc", ctypes.c_void_p), ("phase0", ctypes.c_void_p),
+                ("lpf_taps", ctypes.c_int32), ("lpf", ctypes.c_void_p), ("decim", ctypes.c_int32),
+                ("max_buffer", ctypes.c_uint64), ("out_slots", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_int32), ("slot", ctypes.c_int32), ("tag", ctypes.c_uint64),
+                ("nsamples", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("pfb_frames", ctypes.c_uint64), ("pfb_out", ctypes.c_void_p),
+                ("ddc_outputs", ctypes.c_uint64), ("ddc_ld", ctypes.c_uint64),
+                ("ddc_out", ctypes.c_void_p), ("t_submit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("samples", ctypes.c_uint64), ("bytes_admitted", ctypes.c_uint64),
+                ("bytes_budget", ctypes.c_uint64), ("streams_open", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("gpu_busy_seconds", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); mirrors include/rfchan.h
 SIGNATURES = {
     "rf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -54,6 +85,16 @@ SIGNATURES = {
     "ddc_set_state": (ctypes.c_int, [_P, _P, _SZ]),
     "ddc_reset": (ctypes.c_int, [_P]),
     "ddc_destroy": (ctypes.c_int, [_P]),
+    "rfs_create": (ctypes.c_int, [ctypes.POINTER(_P), _U64, _I32, _I32]),
+    "rfs_stream_footprint": (_U64, [ctypes.POINTER(StreamDesc)]),
+    "rfs_open_stream": (ctypes.c_int, [_P, ctypes.POINTER(StreamDesc), ctypes.POINTER(_I32)]),
+    "rfs_submit": (ctypes.c_int, [_P, _I32, _P, _U64, _U64]),
+    "rfs_poll": (ctypes.c_int, [_P, ctypes.POINTER(Completion), _I32, ctypes.POINTER(_I32), _I32]),
+    "rfs_release": (ctypes.c_int, [_P, _I32, _I32]),
+    "rfs_close_stream": (ctypes.c_int, [_P, _I32]),
+    "rfs_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    "rfs_now": (ctypes.c_double, []),
+    "rfs_destroy": (ctypes.c_int, [_P]),
 }
 
 _lock = threading.Lock()
@@ -270,6 +311,105 @@ class Ddc:
         if getattr(self, "_h", None):
             h, self._h = self._h, None
             check(lib().ddc_destroy(h), "ddc_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Multi-stream serving core (rfs_* calls): admission by device-memory
+    footprint, continuous batching onto grouped kernels, optional hipGraph replay."""
+
+    def __init__(self, hbm_budget_bytes: int, mode: int = RFS_MODE_GRAPH, max_streams: int = 64):
+        self._h = _P()
+        check(lib().rfs_create(ctypes.byref(self._h), int(hbm_budget_bytes), int(mode),
+                               int(max_streams)), "rfs_create")
+        self._keep = {}
+        self._poll_buf = (Completion * 256)()
+
+    @staticmethod
+    def make_desc(pfb=None, ddc=None, max_buffer=1 << 20, out_slots=2):
+        """pfb=(N, M, proto); ddc=(words, phase0 or None, lpf, D).  Returns (desc, keepalive)."""
+        import numpy as np
+        d = StreamDesc()
+        keep = []
+        d.kinds = (RFS_PFB if pfb else 0) | (RFS_DDC if ddc else 0)
+        if pfb:
+            N, M, h = pfb
+            h = np.ascontiguousarray(np.asarray(h, dtype=np.float32).reshape(-1))
+            keep.append(h)
+            d.nchan, d.ntaps, d.proto = int(N), int(M), h.ctypes.data
+        if ddc:
+            words, p0, lpf, D = ddc
+            words = np.ascontiguousarray(np.asarray(words, dtype=np.uint64).reshape(-1))
+            lpf = np.ascontiguousarray(np.asarray(lpf, dtype=np.float32).reshape(-1))
+            keep += [words, lpf]
+            d.ntones, d.phase_inc = int(words.size), words.ctypes.data
+            if p0 is not None:
+                p0 = np.ascontiguousarray(np.asarray(p0, dtype=np.uint64).reshape(-1))
+                keep.append(p0)
+                d.phase0 = p0.ctypes.data
+            d.lpf_taps, d.lpf, d.decim = int(lpf.size), lpf.ctypes.data, int(D)
+        d.max_buffer = int(max_buffer)
+        d.out_slots = int(out_slots)
+        return d, keep
+
+    @staticmethod
+    def footprint(desc) -> int:
+        return int(lib().rfs_stream_footprint(ctypes.byref(desc)))
+
+    def open_stream(self, desc, keep=None) -> int:
+        sid = _I32(-1)
+        check(lib().rfs_open_stream(self._h, ctypes.byref(desc), ctypes.byref(sid)), "rfs_open_stream")
+        self._keep[sid.value] = keep
+        return sid.value
+
+    def try_open_stream(self, desc, keep=None):
+        """Like open_stream, but returns None when the server answers RF_EAGAIN."""
+        sid = _I32(-1)
+        st = lib().rfs_open_stream(self._h, ctypes.byref(desc), ctypes.byref(sid))
+        if st == RF_EAGAIN:
+            return None
+        check(st, "rfs_open_stream")
+        self._keep[sid.value] = keep
+        return sid.value
+
+    def submit(self, sid: int, iq_ptr: int, nsamples: int, tag: int = 0) -> None:
+        check(lib().rfs_submit(self._h, int(sid), iq_ptr, int(nsamples), int(tag)), "rfs_submit")
+
+    def poll(self, max_n: int = 256, timeout_us: int = 0):
+        n = _I32(0)
+        max_n = min(max_n, len(self._poll_buf))
+        check(lib().rfs_poll(self._h, self._poll_buf, max_n, ctypes.byref(n), int(timeout_us)), "rfs_poll")
+        out = []
+        for i in range(n.value):
+            c = self._poll_buf[i]
+            out.append({f: getattr(c, f) for f, _ in Completion._fields_ if f != "pad"})
+        return out
+
+    def release(self, sid: int, slot: int) -> None:
+        check(lib().rfs_release(self._h, int(sid), int(slot)), "rfs_release")
+
+    def close_stream(self, sid: int) -> None:
+        check(lib().rfs_close_stream(self._h, int(sid)), "rfs_close_stream")
+        self._keep.pop(sid, None)
+
+    def stats(self) -> dict:
+        st = Stats()
+        check(lib().rfs_get_stats(self._h, ctypes.byref(st)), "rfs_get_stats")
+        return {f: getattr(st, f) for f, _ in Stats._fields_ if f != "pad"}
+
+    @staticmethod
+    def now() -> float:
+        return float(lib().rfs_now())
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            check(lib().rfs_destroy(h), "rfs_destroy")
 
     def __del__(self):
         try:

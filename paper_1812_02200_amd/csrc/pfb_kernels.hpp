@@ -289,8 +289,19 @@ struct PfbVariant {
     static constexpr int NBUF = DBUF ? 2 : 1;
 };
 
+// LDS of the PFB body, sized for its plan and variant.
+template <int N, int V>
+struct PfbShared {
+    cf frames[PfbVariant<N, V>::NBUF * PfbPlan<N>::LDS];
+    cf tw[lds_tw_count<N>()];
+};
+
+// The whole PFB computation of one logical work-group `lwg` of `G` for the
+// call described by `a`.  Shared by the single-stream kernel and the grouped
+// multi-stream kernel, so a stream's frames are computed by the same
+// instructions either way.
 template <int N, int M, int V>
-__global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_fir_fft(PfbLaunch a)
+__device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, PfbShared<N, V> &sh)
 {
     using P = PfbPlan<N>;
     using VV = PfbVariant<N, V>;
@@ -299,18 +310,12 @@ __global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_fir_fft(PfbLaunch a)
     constexpr int TWL = lds_tw_count<N>();
     // one barrier per phase when double buffered, else two
     constexpr bool SYNC2 = !P::LG_IN_WAVE && !VV::DBUF;
-    __shared__ cf lds_all[VV::NBUF * P::LDS];
-    __shared__ cf twl[TWL];
+    cf *lds_all = sh.frames;
+    cf *twl = sh.tw;
 
     const int tid = threadIdx.x;
     const cf *twg = reinterpret_cast<const cf *>(a.tw);
     for (int i = tid; i < TWL; i += P::WG) twl[i] = twg[i];
-
-    // XCD-aware work-group order: blocks are dealt round-robin to the 8 XCDs,
-    // so give XCD x the contiguous logical range [x*q + min(x,r), ...).
-    const int G = gridDim.x, bid = blockIdx.x;
-    const int xq = G >> 3, xr = G & 7, xcd = bid & 7;
-    const int lwg = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
 
     const VStream vs = a.vs;
     const int64_t vlen = vs.H + vs.n;
@@ -400,20 +405,94 @@ __global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_fir_fft(PfbLaunch a)
     }
 
     // retained history for the next call (sources are read-only this call)
-    for (int64_t i = (int64_t)bid * P::WG + tid; i < a.keep_len; i += (int64_t)G * P::WG)
+    for (int64_t i = (int64_t)lwg * P::WG + tid; i < a.keep_len; i += (int64_t)G * P::WG)
         a.hist_out[i] = vload(vs, a.keep_from + i);
+}
+
+template <int N, int M, int V>
+__global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_fir_fft(PfbLaunch a)
+{
+    __shared__ PfbShared<N, V> sh;
+    // XCD-aware work-group order: blocks are dealt round-robin to the 8 XCDs,
+    // so give XCD x the contiguous logical range [x*q + min(x,r), ...).
+    const int G = gridDim.x, bid = blockIdx.x;
+    const int xq = G >> 3, xr = G & 7, xcd = bid & 7;
+    const int lwg = xcd * xq + (xcd < xr ? xcd : xr) + (bid >> 3);
+    pfb_body<N, M, V>(a, lwg, G, sh);
+}
+
+// Grouped launch: the buffers of many streams with the same (N, M) in one
+// grid.  Work-groups stride over the concatenated logical work-groups of all
+// items (a persistent grid), each item keeping its own history, taps and
+// output.  The item table lives in device memory and is rewritten between
+// launches, so one captured graph serves every batch.
+template <int N, int M>
+__global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_group(const GroupHeader *hdr, const PfbItem *items)
+{
+    __shared__ PfbShared<N, 0> sh;
+    const int nitems = hdr->count;
+    const int64_t total = hdr->total;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = nitems - 1;       // last item with wg_begin <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].wg_begin <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const PfbItem &it = items[lo];
+        pfb_body<N, M, 0>(it.a, (int)(w - it.wg_begin), it.wgs, sh);
+        __syncthreads();   // LDS is reused by the next item
+    }
+}
+
+// Logical work-groups of one call (at least one, for the history copy).
+template <int N>
+inline int64_t pfb_wgs(const PfbLaunch &a)
+{
+    const int64_t runs = (a.F + a.run_len - 1) / a.run_len;
+    int64_t wgs = (runs + PfbPlan<N>::NLG - 1) / PfbPlan<N>::NLG;
+    return wgs < 1 ? 1 : wgs;
 }
 
 template <int N, int M, int V>
 hipError_t launch_pfb_nmv(const PfbLaunch &a, hipStream_t s)
 {
     using P = PfbPlan<N>;
-    const int64_t runs = (a.F + a.run_len - 1) / a.run_len;
-    int64_t wgs = (runs + P::NLG - 1) / P::NLG;
-    if (wgs < 1) wgs = 1;
+    const int64_t wgs = pfb_wgs<N>(a);
     if (wgs > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((pfb_fir_fft<N, M, V>), dim3((unsigned)wgs), dim3(P::WG), 0, s, a);
     return hipGetLastError();
+}
+
+template <int N, int M>
+hipError_t launch_pfb_group_nm(const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((pfb_group<N, M>), dim3((unsigned)grid), dim3(PfbPlan<N>::WG), 0, s, hdr, items);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_pfb_group_n(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    switch (M) {
+    case 1: return launch_pfb_group_nm<N, 1>(hdr, items, grid, s);
+    case 2: return launch_pfb_group_nm<N, 2>(hdr, items, grid, s);
+    case 3: return launch_pfb_group_nm<N, 3>(hdr, items, grid, s);
+    case 4: return launch_pfb_group_nm<N, 4>(hdr, items, grid, s);
+    case 5: return launch_pfb_group_nm<N, 5>(hdr, items, grid, s);
+    case 6: return launch_pfb_group_nm<N, 6>(hdr, items, grid, s);
+    case 7: return launch_pfb_group_nm<N, 7>(hdr, items, grid, s);
+    case 8: return launch_pfb_group_nm<N, 8>(hdr, items, grid, s);
+    case 9: return launch_pfb_group_nm<N, 9>(hdr, items, grid, s);
+    case 10: return launch_pfb_group_nm<N, 10>(hdr, items, grid, s);
+    case 11: return launch_pfb_group_nm<N, 11>(hdr, items, grid, s);
+    case 12: return launch_pfb_group_nm<N, 12>(hdr, items, grid, s);
+    case 13: return launch_pfb_group_nm<N, 13>(hdr, items, grid, s);
+    case 14: return launch_pfb_group_nm<N, 14>(hdr, items, grid, s);
+    case 15: return launch_pfb_group_nm<N, 15>(hdr, items, grid, s);
+    case 16: return launch_pfb_group_nm<N, 16>(hdr, items, grid, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // Dispatch over M (1..16) for a fixed N with the default variant.
@@ -442,6 +521,10 @@ hipError_t launch_pfb_nv(const PfbLaunch &a, hipStream_t s)
 }
 
 // Per-N entry points, each defined in its own translation unit.
+#define RF_DECL_GROUP(n) hipError_t launch_pfb_group_n##n(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s);
+RF_DECL_GROUP(16) RF_DECL_GROUP(32) RF_DECL_GROUP(64) RF_DECL_GROUP(128) RF_DECL_GROUP(256)
+RF_DECL_GROUP(512) RF_DECL_GROUP(1024) RF_DECL_GROUP(2048) RF_DECL_GROUP(4096)
+#undef RF_DECL_GROUP
 hipError_t launch_pfb_n16(const PfbLaunch &a, hipStream_t s);
 hipError_t launch_pfb_n32(const PfbLaunch &a, hipStream_t s);
 hipError_t launch_pfb_n64(const PfbLaunch &a, hipStream_t s);

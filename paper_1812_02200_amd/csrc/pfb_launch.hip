@@ -69,4 +69,46 @@ hipError_t launch_pfb(const PfbLaunch &a, hipStream_t s)
     }
 }
 
+int64_t pfb_launch_wgs(const PfbLaunch &a)
+{
+    switch (a.N) {
+    case 16: return pfb_wgs<16>(a);
+    case 32: return pfb_wgs<32>(a);
+    case 64: return pfb_wgs<64>(a);
+    case 128: return pfb_wgs<128>(a);
+    case 256: return pfb_wgs<256>(a);
+    case 512: return pfb_wgs<512>(a);
+    case 1024: return pfb_wgs<1024>(a);
+    case 2048: return pfb_wgs<2048>(a);
+    case 4096: return pfb_wgs<4096>(a);
+    default: return 0;
+    }
+}
+
+int pfb_group_wg_size(int N)
+{
+    switch (N) {
+    case 2048: return PfbPlan<2048>::WG;
+    case 4096: return PfbPlan<4096>::WG;
+    default: return 256;
+    }
+}
+
+hipError_t launch_pfb_group(int N, int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    if (grid < 1) return hipErrorInvalidValue;
+    switch (N) {
+    case 16: return launch_pfb_group_n16(M, hdr, items, grid, s);
+    case 32: return launch_pfb_group_n32(M, hdr, items, grid, s);
+    case 64: return launch_pfb_group_n64(M, hdr, items, grid, s);
+    case 128: return launch_pfb_group_n128(M, hdr, items, grid, s);
+    case 256: return launch_pfb_group_n256(M, hdr, items, grid, s);
+    case 512: return launch_pfb_group_n512(M, hdr, items, grid, s);
+    case 1024: return launch_pfb_group_n1024(M, hdr, items, grid, s);
+    case 2048: return launch_pfb_group_n2048(M, hdr, items, grid, s);
+    case 4096: return launch_pfb_group_n4096(M, hdr, items, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace rfk

@@ -17,4 +17,9 @@ hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s)
     return launch_pfb_nv<1024, 0>(a, s);
 }
 
+hipError_t launch_pfb_group_n1024(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    return launch_pfb_group_n<1024>(M, hdr, items, grid, s);
+}
+
 }  // namespace rfk

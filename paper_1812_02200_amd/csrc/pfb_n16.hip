@@ -5,4 +5,9 @@ namespace rfk {
 
 hipError_t launch_pfb_n16(const PfbLaunch &a, hipStream_t s) { return launch_pfb_nv<16, 0>(a, s); }
 
+hipError_t launch_pfb_group_n16(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    return launch_pfb_group_n<16>(M, hdr, items, grid, s);
+}
+
 }  // namespace rfk

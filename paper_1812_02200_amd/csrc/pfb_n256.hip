@@ -5,4 +5,9 @@ namespace rfk {
 
 hipError_t launch_pfb_n256(const PfbLaunch &a, hipStream_t s) { return launch_pfb_nv<256, 0>(a, s); }
 
+hipError_t launch_pfb_group_n256(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    return launch_pfb_group_n<256>(M, hdr, items, grid, s);
+}
+
 }  // namespace rfk

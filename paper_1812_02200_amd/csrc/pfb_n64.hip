@@ -5,4 +5,9 @@ namespace rfk {
 
 hipError_t launch_pfb_n64(const PfbLaunch &a, hipStream_t s) { return launch_pfb_nv<64, 0>(a, s); }
 
+hipError_t launch_pfb_group_n64(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
+{
+    return launch_pfb_group_n<64>(M, hdr, items, grid, s);
+}
+
 }  // namespace rfk

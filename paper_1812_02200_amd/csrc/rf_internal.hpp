@@ -48,6 +48,28 @@ struct DdcLaunch {
     int32_t grid;           // work-groups to launch (persistent)
 };
 
+// Grouped launches: a device-side header and item table, rewritten between
+// launches (the kernels read the count and the work-group total from memory,
+// so a captured graph can be replayed for every batch).
+struct GroupHeader {
+    int32_t count;          // items
+    int32_t pad;
+    int64_t total;          // logical work-groups (PFB) or work units (DDC)
+};
+
+struct PfbItem {
+    PfbLaunch a;
+    int64_t wg_begin;       // first logical work-group of this item
+    int32_t wgs;            // logical work-groups of this item
+    int32_t pad;
+};
+
+// Logical work-groups a single-stream PFB launch of `a` uses.
+int64_t pfb_launch_wgs(const PfbLaunch &a);
+hipError_t launch_pfb_group(int N, int M, const GroupHeader *hdr, const PfbItem *items, int grid,
+                            hipStream_t s);
+int pfb_group_wg_size(int N);
+
 // Twiddle table size (float pairs) for an N-point plan.
 int pfb_twiddle_count(int N);
 // Fill the twiddle table (host memory, float pairs) for an N-point plan.
@@ -64,6 +86,15 @@ void pfb_mfma_table_fill(float *t);
 int pfb_default_run_len(int N, int M, int64_t F);
 
 hipError_t launch_ddc(const DdcLaunch &a, hipStream_t s);
+
+constexpr int kDdcGroupWG = 256;   // threads (= tones per chunk) of the grouped DDC kernel
+struct DdcItem {
+    DdcLaunch a;
+    int64_t unit_begin;     // first work unit of this item
+};
+// Work units of one item in a grouped launch: (tone chunk, output) pairs + 1 tail.
+int64_t ddc_group_units(const DdcLaunch &a);
+hipError_t launch_ddc_group(const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s);
 int ddc_default_grid(int ntones, int64_t nout);
 
 // Number of float entries of the half-wave sine table.

@@ -15,6 +15,7 @@
 #include <string>
 
 #include "../../include/rfchan.h"
+#include "rf_handles.hpp"
 #include "rf_internal.hpp"
 
 #define RF_VERSION (0 * 10000 + 1 * 100 + 0)
@@ -171,6 +172,66 @@ uint64_t pfb_count(const rf_pfb *p, uint64_t n)
 
 }  // namespace
 
+namespace rfi {
+
+int set_error(int status, const char *msg) { return fail(status, "%s", msg); }
+
+int pfb_prepare(rf_pfb *p, const int16_t *iq_dev, uint64_t nsamples, float *out_dev, uint64_t out_cap_frames,
+                rfk::PfbLaunch *a, uint64_t *frames)
+{
+    if (!p) return fail(RF_EINVAL, "pfb_process: handle is NULL");
+    if (nsamples > p->max_samples)
+        return fail(RF_EINVAL, "pfb_process: nsamples=%llu exceeds max_samples_per_call=%llu",
+                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
+    if (nsamples > 0 && (!iq_dev || !aligned(iq_dev, 4)))
+        return fail(RF_EINVAL, "pfb_process: iq_dev must be a non-NULL 4-byte aligned device pointer");
+    const uint64_t F = pfb_count(p, nsamples);
+    if (F > out_cap_frames)
+        return fail(RF_ECAPACITY, "pfb_process: %llu frames need more than out_cap_frames=%llu",
+                    (unsigned long long)F, (unsigned long long)out_cap_frames);
+    if (F > 0 && (!out_dev || !aligned(out_dev, 8)))
+        return fail(RF_EINVAL, "pfb_process: out_dev must be a non-NULL 8-byte aligned device pointer");
+    const int64_t vlen = p->H + (int64_t)nsamples;
+    a->vs.hist = p->d_hist[p->cur];
+    a->vs.in = reinterpret_cast<const uint32_t *>(iq_dev);
+    a->vs.H = p->H;
+    a->vs.n = (int64_t)nsamples;
+    a->hist_out = p->d_hist[p->cur ^ 1];
+    a->keep_from = (int64_t)F * p->N;
+    a->keep_len = vlen - a->keep_from;
+    a->out = out_dev;
+    a->taps = p->d_taps;
+    a->tw = p->d_tw;
+    a->F = (int64_t)F;
+    a->run_len = p->run_len > 0 ? p->run_len : rfk::pfb_default_run_len(p->N, p->M, (int64_t)F);
+    a->N = p->N;
+    a->M = p->M;
+    a->variant = p->variant;
+    *frames = F;
+    return RF_OK;
+}
+
+void pfb_commit(rf_pfb *p, const rfk::PfbLaunch &a, uint64_t nsamples, uint64_t F, hipStream_t s)
+{
+    p->order.after(s);
+    p->cur ^= 1;
+    p->H = a.keep_len;
+    p->S += nsamples;
+    p->frames += F;
+}
+
+int pfb_device(const rf_pfb *p) { return p->device; }
+int pfb_mode(const rf_pfb *p) { return p->mode; }
+size_t pfb_footprint(int N, int M, int mode)
+{
+    const size_t span = (size_t)N * M;
+    const size_t tw = mode == RF_DFT_FFT_F32 ? (size_t)rfk::pfb_twiddle_count(N) * 8
+                                             : (size_t)rfk::pfb_mfma_table_floats() * 4;
+    return span * 4 /* taps */ + tw + 2 * span * 4 /* history */;
+}
+
+}  // namespace rfi
+
 extern "C" {
 
 const char *rf_strerror(int status)
@@ -269,54 +330,22 @@ int pfb_process(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out
                 uint64_t *frames_out, void *hip_stream)
 {
     if (frames_out) *frames_out = 0;
-    if (!p) return fail(RF_EINVAL, "pfb_process: handle is NULL");
-    if (nsamples > p->max_samples)
-        return fail(RF_EINVAL, "pfb_process: nsamples=%llu exceeds max_samples_per_call=%llu",
-                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
-    if (nsamples > 0 && (!iq_dev || !aligned(iq_dev, 4)))
-        return fail(RF_EINVAL, "pfb_process: iq_dev must be a non-NULL 4-byte aligned device pointer");
-    const uint64_t F = pfb_count(p, nsamples);
-    if (F > out_cap_frames)
-        return fail(RF_ECAPACITY, "pfb_process: %llu frames need more than out_cap_frames=%llu",
-                    (unsigned long long)F, (unsigned long long)out_cap_frames);
-    if (F > 0 && (!out_dev || !aligned(out_dev, 8)))
-        return fail(RF_EINVAL, "pfb_process: out_dev must be a non-NULL 8-byte aligned device pointer");
-    if (nsamples == 0) return RF_OK;
+    rfk::PfbLaunch a;
+    uint64_t F = 0;
+    int rc = rfi::pfb_prepare(p, iq_dev, nsamples, out_dev, out_cap_frames, &a, &F);
+    if (rc || nsamples == 0) return rc;
 
     DeviceGuard dg(p->device);
     HIP_TRY(dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
-    int rc = p->order.before(s);
+    rc = p->order.before(s);
     if (rc) return rc;
-
-    const int64_t vlen = p->H + (int64_t)nsamples;
-    rfk::PfbLaunch a;
-    a.vs.hist = p->d_hist[p->cur];
-    a.vs.in = reinterpret_cast<const uint32_t *>(iq_dev);
-    a.vs.H = p->H;
-    a.vs.n = (int64_t)nsamples;
-    a.hist_out = p->d_hist[p->cur ^ 1];
-    a.keep_from = (int64_t)F * p->N;
-    a.keep_len = vlen - a.keep_from;
-    a.out = out_dev;
-    a.taps = p->d_taps;
-    a.tw = p->d_tw;
-    a.F = (int64_t)F;
-    a.run_len = p->run_len > 0 ? p->run_len : rfk::pfb_default_run_len(p->N, p->M, (int64_t)F);
-    a.N = p->N;
-    a.M = p->M;
-    a.variant = p->variant;
     if (p->mode == RF_DFT_FFT_F32)
         HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
     else
         HIP_TRY(rfk::launch_pfb_mfma(a, p->mode == RF_DFT_MFMA_BF16X2 ? rfk::RF_PREC_BF16 : rfk::RF_PREC_F16, s),
                 "pfb mfma kernel launch");
-
-    p->order.after(s);
-    p->cur ^= 1;
-    p->H = a.keep_len;
-    p->S += nsamples;
-    p->frames += F;
+    rfi::pfb_commit(p, a, nsamples, F, s);
     if (frames_out) *frames_out = F;
     return RF_OK;
 }
@@ -500,6 +529,80 @@ DdcPlan ddc_plan(const rf_ddc *p, uint64_t n)
     return r;
 }
 
+}  // namespace
+
+namespace rfi {
+
+int ddc_prepare(rf_ddc *p, const int16_t *iq_dev, uint64_t nsamples, float *out_dev, uint64_t ld,
+                rfk::DdcLaunch *a, uint64_t *nout)
+{
+    if (!p) return fail(RF_EINVAL, "ddc_process: handle is NULL");
+    if (nsamples > p->max_samples)
+        return fail(RF_EINVAL, "ddc_process: nsamples=%llu exceeds max_samples_per_call=%llu",
+                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
+    if (nsamples > 0 && (!iq_dev || !aligned(iq_dev, 4)))
+        return fail(RF_EINVAL, "ddc_process: iq_dev must be a non-NULL 4-byte aligned device pointer");
+    const DdcPlan pl = ddc_plan(p, nsamples);
+    if (pl.nout > 0) {
+        if (ld < pl.nout)
+            return fail(RF_ECAPACITY, "ddc_process: ld=%llu < %llu outputs", (unsigned long long)ld,
+                        (unsigned long long)pl.nout);
+        if (!out_dev || !aligned(out_dev, 8))
+            return fail(RF_EINVAL, "ddc_process: out_dev must be a non-NULL 8-byte aligned device pointer");
+    }
+    a->vs.hist = p->d_hist[p->cur];
+    a->vs.in = reinterpret_cast<const uint32_t *>(iq_dev) + pl.nskip;
+    a->vs.H = p->skip > 0 ? 0 : p->H;
+    a->vs.n = (int64_t)pl.neff;
+    a->hist_out = p->d_hist[p->cur ^ 1];
+    a->keep_from = (int64_t)pl.keep_from;
+    a->keep_len = (int64_t)pl.keep_len;
+    a->out = out_dev;
+    a->ld = (int64_t)ld;
+    a->wrev = p->d_wrev;
+    a->inc = p->d_inc;
+    a->phi0 = p->d_phi0;
+    a->sintab = p->d_tab;
+    a->base_abs = p->nnext * (uint64_t)p->D;
+    a->nout = (int64_t)pl.nout;
+    a->phase_out = p->d_phase;
+    a->phase_at = p->S + nsamples;
+    a->T = p->T;
+    a->D = p->D;
+    a->ntones = p->ntones;
+    const int wg = p->ntones <= 64 ? 64 : p->ntones <= 128 ? 128 : p->ntones <= 256 ? 256
+                   : p->ntones <= 512 ? 512 : 1024;
+    const int64_t items = (int64_t)((p->ntones + wg - 1) / wg) * (int64_t)pl.nout;
+    int64_t grid = p->grid > 0 ? p->grid : p->cus;
+    if (grid > items) grid = items;
+    if (grid < 1) grid = 1;
+    a->grid = (int32_t)grid;
+    *nout = pl.nout;
+    return RF_OK;
+}
+
+void ddc_commit(rf_ddc *p, uint64_t nsamples, hipStream_t s)
+{
+    const DdcPlan pl = ddc_plan(p, nsamples);
+    p->order.after(s);
+    p->cur ^= 1;
+    p->S += nsamples;
+    p->nnext += pl.nout;
+    p->H = (int64_t)pl.keep_len;
+    p->skip = pl.skip_after;
+}
+
+int ddc_device(const rf_ddc *p) { return p->device; }
+int ddc_ntones(const rf_ddc *p) { return p->ntones; }
+size_t ddc_footprint(int ntones, int T)
+{
+    return (size_t)ntones * 8 * 3 + (size_t)T * 4 + (size_t)rfk::kSinTabLen * 4 + 2 * (size_t)T * 4;
+}
+
+}  // namespace rfi
+
+namespace {
+
 // Half-wave sine table: S[i] = sin(2 pi i / 2^16), i in [0, 2^15), built from
 // the quarter wave q[j] = fp32(sin(pi j / 2^15)) so every entry equals the
 // corresponding entry of the full FP32 table up to sign.
@@ -599,68 +702,19 @@ int ddc_process(rf_ddc_t p, const int16_t *iq_dev, uint64_t nsamples, float *out
                 void *hip_stream)
 {
     if (nout) *nout = 0;
-    if (!p) return fail(RF_EINVAL, "ddc_process: handle is NULL");
-    if (nsamples > p->max_samples)
-        return fail(RF_EINVAL, "ddc_process: nsamples=%llu exceeds max_samples_per_call=%llu",
-                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
-    if (nsamples > 0 && (!iq_dev || !aligned(iq_dev, 4)))
-        return fail(RF_EINVAL, "ddc_process: iq_dev must be a non-NULL 4-byte aligned device pointer");
-    const DdcPlan pl = ddc_plan(p, nsamples);
-    if (pl.nout > 0) {
-        if (ld < pl.nout)
-            return fail(RF_ECAPACITY, "ddc_process: ld=%llu < %llu outputs", (unsigned long long)ld,
-                        (unsigned long long)pl.nout);
-        if (!out_dev || !aligned(out_dev, 8))
-            return fail(RF_EINVAL, "ddc_process: out_dev must be a non-NULL 8-byte aligned device pointer");
-    }
-    if (nsamples == 0) return RF_OK;
+    rfk::DdcLaunch a;
+    uint64_t no = 0;
+    int rc = rfi::ddc_prepare(p, iq_dev, nsamples, out_dev, ld, &a, &no);
+    if (rc || nsamples == 0) return rc;
 
     DeviceGuard dg(p->device);
     HIP_TRY(dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
-    int rc = p->order.before(s);
+    rc = p->order.before(s);
     if (rc) return rc;
-
-    rfk::DdcLaunch a;
-    a.vs.hist = p->d_hist[p->cur];
-    a.vs.in = reinterpret_cast<const uint32_t *>(iq_dev) + pl.nskip;
-    a.vs.H = p->skip > 0 ? 0 : p->H;
-    a.vs.n = (int64_t)pl.neff;
-    a.hist_out = p->d_hist[p->cur ^ 1];
-    a.keep_from = (int64_t)pl.keep_from;
-    a.keep_len = (int64_t)pl.keep_len;
-    a.out = out_dev;
-    a.ld = (int64_t)ld;
-    a.wrev = p->d_wrev;
-    a.inc = p->d_inc;
-    a.phi0 = p->d_phi0;
-    a.sintab = p->d_tab;
-    a.base_abs = p->nnext * (uint64_t)p->D;
-    a.nout = (int64_t)pl.nout;
-    a.phase_out = p->d_phase;
-    a.phase_at = p->S + nsamples;
-    a.T = p->T;
-    a.D = p->D;
-    a.ntones = p->ntones;
-    {
-        const int wg = p->ntones <= 64 ? 64 : p->ntones <= 128 ? 128 : p->ntones <= 256 ? 256
-                       : p->ntones <= 512 ? 512 : 1024;
-        const int64_t tc = (p->ntones + wg - 1) / wg;
-        int64_t items = tc * (int64_t)pl.nout;
-        int64_t grid = p->grid > 0 ? p->grid : p->cus;
-        if (grid > items) grid = items;
-        if (grid < 1) grid = 1;
-        a.grid = (int32_t)grid;
-    }
     HIP_TRY(rfk::launch_ddc(a, s), "ddc kernel launch");
-
-    p->order.after(s);
-    p->cur ^= 1;
-    p->S += nsamples;
-    p->nnext += pl.nout;
-    p->H = (int64_t)pl.keep_len;
-    p->skip = pl.skip_after;
-    if (nout) *nout = pl.nout;
+    rfi::ddc_commit(p, nsamples, s);
+    if (nout) *nout = no;
     return RF_OK;
 }
 

@@ -1,0 +1,705 @@
+// serve.hip -- multi-stream serving core: admission by device-memory
+// footprint, continuous batching, grouped persistent kernels, hipGraph replay.
+//
+// The paper's readout moves buffers between host threads through lock-free
+// queues of pointers to pre-allocated memory and hands them to a GPU
+// processing thread (Sec. III, Fig. 2).  Here one scheduler thread owns the
+// GPU: clients queue buffers per stream, and the scheduler repeatedly takes
+// the oldest queued buffer of every stream that has a free output slot, turns
+// them into item tables (one per (N, M) class of PFB streams, one for all DDC
+// banks), uploads the tables and launches one grouped kernel per table.  A
+// stream's consecutive buffers land in consecutive batches on the same HIP
+// stream, so its history and phase carry over without any host wait.  Up to
+// two batches are in flight: while one runs, the next is prepared.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/rfchan.h"
+#include "rf_handles.hpp"
+#include "rf_internal.hpp"
+
+namespace {
+
+using rfi::set_error;
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    const int16_t *iq;
+    uint64_t n;
+    uint64_t tag;
+    double t_submit;
+};
+
+struct Stream {
+    int id = -1;
+    int kinds = 0;
+    rf_pfb *pfb = nullptr;
+    rf_ddc *ddc = nullptr;
+    int N = 0, M = 0, ntones = 0;
+    uint64_t max_buffer = 0;
+    uint64_t pfb_cap = 0;      // frames per output slot
+    uint64_t ddc_ld = 0;       // outputs per tone per output slot
+    int nslots = 0;
+    std::vector<float *> pfb_slot, ddc_slot;
+    std::vector<int> free_slots;
+    std::deque<Request> queue;
+    int inflight = 0;
+    size_t footprint = 0;
+    bool closing = false;
+};
+
+struct Done {
+    int stream, slot;
+    Request req;
+    uint64_t pfb_frames, ddc_outputs, ddc_ld;
+    const float *pfb_out, *ddc_out;
+    double t_launch;
+};
+
+// Device/pinned layout of one batch's item tables.
+struct Blob {
+    void *host = nullptr;      // pinned
+    void *dev = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;   // completion of the batch that last used this blob
+    bool busy = false;
+    double t_launch = 0;
+    std::vector<Done> done;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_version = -1;
+};
+
+}  // namespace
+
+struct rfs_server {
+    int device = 0;
+    int mode = RFS_MODE_BATCHED;
+    int max_streams = 64;
+    int cus = 256;
+    uint64_t budget = 0, admitted = 0;
+    hipStream_t hs = nullptr;
+    std::vector<hipStream_t> branch;   // fork streams for graph capture
+    std::vector<hipEvent_t> fork_ev;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<int, Stream *> streams;
+    int next_id = 0;
+    std::deque<rfs_completion> completions;
+    std::thread thr;
+    std::atomic<bool> stop{false};
+    Blob blobs[2];
+    int next_blob = 0;
+    // class table: distinct (N, M) of open PFB streams -> table index
+    std::vector<std::pair<int, int>> classes;
+    int class_version = 0;
+    size_t region = 0;                 // bytes per table region
+    rfs_stats st{};
+    std::string fatal;
+};
+
+namespace {
+
+constexpr int kMaxBranches = 4;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t region_bytes(int max_items)
+{
+    const size_t item = std::max(sizeof(rfk::PfbItem), sizeof(rfk::DdcItem));
+    return align_up(sizeof(rfk::GroupHeader), 256) + align_up(item * (size_t)max_items, 256);
+}
+
+// Tables: [PFB class 0] ... [PFB class C-1] [DDC]; C fixed by class_version.
+rfk::GroupHeader *hdr_at(void *base, size_t region, int t)
+{
+    return reinterpret_cast<rfk::GroupHeader *>((char *)base + region * t);
+}
+template <typename ItemT>
+ItemT *items_at(void *base, size_t region, int t)
+{
+    return reinterpret_cast<ItemT *>((char *)base + region * t + align_up(sizeof(rfk::GroupHeader), 256));
+}
+
+uint64_t slot_frames(int N, int M, uint64_t max_buffer) { return ((uint64_t)N * M + max_buffer) / N + 1; }
+uint64_t slot_outputs(int T, int D, uint64_t max_buffer) { return ((uint64_t)T + max_buffer) / D + 2; }
+
+size_t footprint_of(const rfs_stream_desc *d)
+{
+    size_t f = 0;
+    const int slots = d->out_slots > 0 ? d->out_slots : 1;
+    if (d->kinds & RFS_PFB) {
+        f += rfi::pfb_footprint(d->nchan, d->ntaps, RF_DFT_FFT_F32);
+        f += (size_t)slots * slot_frames(d->nchan, d->ntaps, d->max_buffer) * d->nchan * 8;
+    }
+    if (d->kinds & RFS_DDC) {
+        f += rfi::ddc_footprint(d->ntones, d->lpf_taps);
+        f += (size_t)slots * d->ntones * slot_outputs(d->lpf_taps, d->decim, d->max_buffer) * 8;
+    }
+    return f;
+}
+
+void free_stream(Stream *s)
+{
+    if (!s) return;
+    if (s->pfb) pfb_destroy(s->pfb);
+    if (s->ddc) ddc_destroy(s->ddc);
+    for (float *p : s->pfb_slot) (void)hipFree(p);
+    for (float *p : s->ddc_slot) (void)hipFree(p);
+    delete s;
+}
+
+int class_index(rfs_server *S, int N, int M)
+{
+    for (size_t i = 0; i < S->classes.size(); ++i)
+        if (S->classes[i].first == N && S->classes[i].second == M) return (int)i;
+    return -1;
+}
+
+// Recompute the class list from the open streams (caller holds mu).
+void rebuild_classes(rfs_server *S)
+{
+    std::vector<std::pair<int, int>> c;
+    for (auto &kv : S->streams)
+        if (kv.second->kinds & RFS_PFB) {
+            std::pair<int, int> k(kv.second->N, kv.second->M);
+            if (std::find(c.begin(), c.end(), k) == c.end()) c.push_back(k);
+        }
+    std::sort(c.begin(), c.end());
+    if (c != S->classes) {
+        S->classes = c;
+        ++S->class_version;
+    }
+}
+
+int pfb_grid(rfs_server *S, int N) { return N >= 2048 ? S->cus : 2 * S->cus; }
+
+// Capture the batch graph for the current class list into blob b:
+// upload tables, then fork: one grouped kernel per class and the DDC kernel on
+// parallel branches, join.
+int capture_graph(rfs_server *S, Blob &b)
+{
+    if (b.exec) {
+        (void)hipGraphExecDestroy(b.exec);
+        b.exec = nullptr;
+    }
+    if (b.graph) {
+        (void)hipGraphDestroy(b.graph);
+        b.graph = nullptr;
+    }
+    const int C = (int)S->classes.size();
+    hipError_t e = hipStreamBeginCapture(S->hs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return set_error(RF_EDEVICE, "hipStreamBeginCapture failed");
+    hipError_t err = hipMemcpyAsync(b.dev, b.host, S->region * (C + 1), hipMemcpyHostToDevice, S->hs);
+    if (err == hipSuccess) err = hipEventRecord(S->fork_ev[0], S->hs);
+    for (int t = 0; t <= C && err == hipSuccess; ++t) {
+        hipStream_t bs = S->branch[t % kMaxBranches];
+        err = hipStreamWaitEvent(bs, S->fork_ev[0], 0);
+        if (err != hipSuccess) break;
+        const rfk::GroupHeader *h = hdr_at(b.dev, S->region, t);
+        if (t < C)
+            err = rfk::launch_pfb_group(S->classes[t].first, S->classes[t].second, h,
+                                        items_at<rfk::PfbItem>(b.dev, S->region, t),
+                                        pfb_grid(S, S->classes[t].first), bs);
+        else
+            err = rfk::launch_ddc_group(h, items_at<rfk::DdcItem>(b.dev, S->region, t), S->cus, bs);
+    }
+    const int used = std::min(C + 1, kMaxBranches);   // join only the branches the capture forked
+    for (int k = 0; k < used && err == hipSuccess; ++k) {
+        err = hipEventRecord(S->fork_ev[1 + k], S->branch[k]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(S->hs, S->fork_ev[1 + k], 0);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(S->hs, &g);
+    if (err != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return set_error(RF_EDEVICE, "graph capture of the batch failed");
+    }
+    e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return set_error(RF_EDEVICE, "hipGraphInstantiate failed");
+    }
+    b.graph = g;
+    b.graph_version = S->class_version;
+    return RF_OK;
+}
+
+// Pick one request per eligible stream and prepare its launches (caller holds
+// mu).  SEQUENTIAL mode takes only the oldest request overall.
+bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunch> &pl,
+                std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who)
+{
+    std::vector<Stream *> cand;
+    for (auto &kv : S->streams) {
+        Stream *s = kv.second;
+        if (!s->queue.empty() && !s->free_slots.empty()) cand.push_back(s);
+    }
+    if (cand.empty()) return false;
+    std::sort(cand.begin(), cand.end(),
+              [](Stream *a, Stream *b) { return a->queue.front().t_submit < b->queue.front().t_submit; });
+    if (S->mode == RFS_MODE_SEQUENTIAL) cand.resize(1);
+    for (Stream *s : cand) {
+        Request r = s->queue.front();
+        const int slot = s->free_slots.back();
+        Done d{};
+        d.stream = s->id;
+        d.slot = slot;
+        d.req = r;
+        rfk::PfbLaunch a{};
+        rfk::DdcLaunch b{};
+        bool ok = true;
+        if (s->pfb) {
+            uint64_t F = 0;
+            ok = rfi::pfb_prepare(s->pfb, r.iq, r.n, s->pfb_slot[slot], s->pfb_cap, &a, &F) == RF_OK;
+            d.pfb_frames = F;
+            d.pfb_out = s->pfb_slot[slot];
+        }
+        if (ok && s->ddc) {
+            uint64_t no = 0;
+            ok = rfi::ddc_prepare(s->ddc, r.iq, r.n, s->ddc_slot[slot], s->ddc_ld, &b, &no) == RF_OK;
+            d.ddc_outputs = no;
+            d.ddc_ld = s->ddc_ld;
+            d.ddc_out = s->ddc_slot[slot];
+        }
+        if (!ok) {   // cannot happen for validated submissions; drop the request with an error
+            s->queue.pop_front();
+            rfs_completion c{};
+            c.stream = s->id;
+            c.slot = -1;
+            c.tag = r.tag;
+            c.nsamples = r.n;
+            c.status = RF_EINVAL;
+            c.t_submit = r.t_submit;
+            c.t_done = now_s();
+            S->completions.push_back(c);
+            continue;
+        }
+        s->queue.pop_front();
+        s->free_slots.pop_back();
+        s->inflight++;
+        out.push_back(d);
+        pl.push_back(a);
+        dl.push_back(b);
+        who.push_back(s);
+    }
+    return !out.empty();
+}
+
+// Enqueue a batch.  Returns RF_OK or an error (GPU failure).
+int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk::PfbLaunch> &pl,
+                 std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who)
+{
+    if (S->mode == RFS_MODE_SEQUENTIAL) {
+        for (size_t i = 0; i < who.size(); ++i) {
+            Stream *s = who[i];
+            if (s->pfb && dn[i].req.n) {
+                hipError_t e = rfk::launch_pfb(pl[i], S->hs);
+                if (e != hipSuccess) return set_error(RF_EDEVICE, "pfb launch failed");
+                rfi::pfb_commit(s->pfb, pl[i], dn[i].req.n, dn[i].pfb_frames, S->hs);
+            }
+            if (s->ddc && dn[i].req.n) {
+                hipError_t e = rfk::launch_ddc(dl[i], S->hs);
+                if (e != hipSuccess) return set_error(RF_EDEVICE, "ddc launch failed");
+                rfi::ddc_commit(s->ddc, dn[i].req.n, S->hs);
+            }
+        }
+        return RF_OK;
+    }
+    const int C = (int)S->classes.size();
+    for (int t = 0; t <= C; ++t) {
+        rfk::GroupHeader *h = hdr_at(b.host, S->region, t);
+        h->count = 0;
+        h->total = 0;
+    }
+    for (size_t i = 0; i < who.size(); ++i) {
+        Stream *s = who[i];
+        if (!dn[i].req.n) continue;
+        if (s->pfb) {
+            const int t = class_index(S, s->N, s->M);
+            rfk::GroupHeader *h = hdr_at(b.host, S->region, t);
+            rfk::PfbItem &it = items_at<rfk::PfbItem>(b.host, S->region, t)[h->count];
+            it.a = pl[i];
+            it.a.variant = 0;
+            it.wg_begin = h->total;
+            it.wgs = (int32_t)rfk::pfb_launch_wgs(pl[i]);
+            h->total += it.wgs;
+            h->count++;
+        }
+        if (s->ddc) {
+            rfk::GroupHeader *h = hdr_at(b.host, S->region, C);
+            rfk::DdcItem &it = items_at<rfk::DdcItem>(b.host, S->region, C)[h->count];
+            it.a = dl[i];
+            it.unit_begin = h->total;
+            h->total += rfk::ddc_group_units(dl[i]);
+            h->count++;
+        }
+    }
+    if (S->mode == RFS_MODE_GRAPH) {
+        if (b.graph_version != S->class_version) {
+            int rc = capture_graph(S, b);
+            if (rc) return rc;
+        }
+        if (hipGraphLaunch(b.exec, S->hs) != hipSuccess) return set_error(RF_EDEVICE, "hipGraphLaunch failed");
+    } else {
+        hipError_t e = hipMemcpyAsync(b.dev, b.host, S->region * (C + 1), hipMemcpyHostToDevice, S->hs);
+        if (e != hipSuccess) return set_error(RF_EDEVICE, "table upload failed");
+        for (int t = 0; t <= C; ++t) {
+            const rfk::GroupHeader *hh = hdr_at(b.host, S->region, t);
+            if (hh->count == 0) continue;
+            const rfk::GroupHeader *hd = hdr_at(b.dev, S->region, t);
+            if (t < C) {
+                const int grid = (int)std::min<int64_t>(hh->total, pfb_grid(S, S->classes[t].first));
+                e = rfk::launch_pfb_group(S->classes[t].first, S->classes[t].second, hd,
+                                          items_at<rfk::PfbItem>(b.dev, S->region, t), grid, S->hs);
+            } else {
+                const int grid = (int)std::min<int64_t>(hh->total, S->cus);
+                e = rfk::launch_ddc_group(hd, items_at<rfk::DdcItem>(b.dev, S->region, t), grid, S->hs);
+            }
+            if (e != hipSuccess) return set_error(RF_EDEVICE, "grouped launch failed");
+        }
+    }
+    for (size_t i = 0; i < who.size(); ++i) {
+        Stream *s = who[i];
+        if (!dn[i].req.n) continue;
+        if (s->pfb) rfi::pfb_commit(s->pfb, pl[i], dn[i].req.n, dn[i].pfb_frames, S->hs);
+        if (s->ddc) rfi::ddc_commit(s->ddc, dn[i].req.n, S->hs);
+    }
+    return RF_OK;
+}
+
+void finish_blob(rfs_server *S, Blob &b)
+{
+    const double t = now_s();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (Done &d : b.done) {
+        rfs_completion c{};
+        c.stream = d.stream;
+        c.slot = d.slot;
+        c.tag = d.req.tag;
+        c.nsamples = d.req.n;
+        c.status = RF_OK;
+        c.pfb_frames = d.pfb_frames;
+        c.pfb_out = d.pfb_out;
+        c.ddc_outputs = d.ddc_outputs;
+        c.ddc_ld = d.ddc_ld;
+        c.ddc_out = d.ddc_out;
+        c.t_submit = d.req.t_submit;
+        c.t_launch = d.t_launch;
+        c.t_done = t;
+        S->completions.push_back(c);
+        auto it = S->streams.find(d.stream);
+        if (it != S->streams.end()) it->second->inflight--;
+        S->st.requests++;
+        S->st.samples += d.req.n;
+    }
+    S->st.batches++;
+    S->st.gpu_busy_seconds += t - b.t_launch;
+    b.done.clear();
+    b.busy = false;
+    S->cv_done.notify_all();
+}
+
+void scheduler(rfs_server *S)
+{
+    (void)hipSetDevice(S->device);
+    std::vector<Done> dn;
+    std::vector<rfk::PfbLaunch> pl;
+    std::vector<rfk::DdcLaunch> dl;
+    std::vector<Stream *> who;
+    while (true) {
+        // retire finished batches, oldest first
+        for (int k = 0; k < 2; ++k) {
+            Blob &b = S->blobs[(S->next_blob + k) & 1];
+            if (b.busy && hipEventQuery(b.ev) == hipSuccess) finish_blob(S, b);
+        }
+        Blob &b = S->blobs[S->next_blob];
+        if (b.busy) {   // both blobs in flight: wait for the older one
+            (void)hipEventSynchronize(b.ev);
+            finish_blob(S, b);
+        }
+        dn.clear();
+        pl.clear();
+        dl.clear();
+        who.clear();
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop && S->blobs[0].busy == false && S->blobs[1].busy == false) {
+                bool pending = false;
+                for (auto &kv : S->streams) pending |= !kv.second->queue.empty();
+                if (!pending) break;
+            }
+            if (!form_batch(S, dn, pl, dl, who)) {
+                const bool any_busy = S->blobs[0].busy || S->blobs[1].busy;
+                if (S->stop && !any_busy) break;
+                if (any_busy) {
+                    lk.unlock();
+                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                } else {
+                    S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                }
+                continue;
+            }
+            int rc = launch_batch(S, b, dn, pl, dl, who);
+            if (rc) {
+                S->fatal = rf_last_error();
+                for (Stream *s : who) s->inflight--;
+                S->stop = true;
+                break;
+            }
+        }
+        b.t_launch = now_s();
+        for (Done &d : dn) d.t_launch = b.t_launch;
+        b.done = dn;
+        (void)hipEventRecord(b.ev, S->hs);
+        b.busy = true;
+        S->next_blob ^= 1;
+    }
+    for (int k = 0; k < 2; ++k)
+        if (S->blobs[k].busy) {
+            (void)hipEventSynchronize(S->blobs[k].ev);
+            finish_blob(S, S->blobs[k]);
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+double rfs_now(void) { return now_s(); }
+
+uint64_t rfs_stream_footprint(const rfs_stream_desc *d) { return d ? footprint_of(d) : 0; }
+
+int rfs_create(rfs_t *out, uint64_t hbm_budget_bytes, int32_t mode, int32_t max_streams)
+{
+    if (!out) return set_error(RF_EINVAL, "rfs_create: out is NULL");
+    *out = nullptr;
+    if (mode < RFS_MODE_SEQUENTIAL || mode > RFS_MODE_GRAPH) return set_error(RF_EINVAL, "rfs_create: bad mode");
+    if (max_streams < 1 || max_streams > 4096) return set_error(RF_EINVAL, "rfs_create: max_streams out of range");
+    rfs_server *S = new (std::nothrow) rfs_server;
+    if (!S) return set_error(RF_ENOMEM, "rfs_create: host allocation");
+    S->mode = mode;
+    S->max_streams = max_streams;
+    S->budget = hbm_budget_bytes;
+    S->st.bytes_budget = hbm_budget_bytes;
+    bool ok = hipGetDevice(&S->device) == hipSuccess;
+    int cus = 0;
+    if (ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && cus > 0)
+        S->cus = cus;
+    ok = ok && hipStreamCreateWithFlags(&S->hs, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; ok && k < kMaxBranches; ++k) {
+        hipStream_t bs = nullptr;
+        ok = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) == hipSuccess;
+        if (ok) S->branch.push_back(bs);
+    }
+    for (int k = 0; ok && k < 1 + kMaxBranches; ++k) {
+        hipEvent_t ev = nullptr;
+        ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (ok) S->fork_ev.push_back(ev);
+    }
+    // item tables sized for every open stream in up to max_streams classes + DDC
+    S->region = region_bytes(max_streams);
+    const size_t bytes = S->region * (size_t)(max_streams + 1);
+    for (int k = 0; ok && k < 2; ++k) {
+        Blob &b = S->blobs[k];
+        b.bytes = bytes;
+        ok = hipHostMalloc(&b.host, bytes, hipHostMallocDefault) == hipSuccess &&
+             hipMalloc(&b.dev, bytes) == hipSuccess &&
+             hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess;
+        if (ok) memset(b.host, 0, bytes);
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        rfs_destroy(S);
+        return set_error(RF_EDEVICE, "rfs_create: HIP resource allocation failed");
+    }
+    S->thr = std::thread(scheduler, S);
+    *out = S;
+    return RF_OK;
+}
+
+int rfs_open_stream(rfs_t S, const rfs_stream_desc *d, int32_t *id)
+{
+    if (!S || !d || !id) return set_error(RF_EINVAL, "rfs_open_stream: NULL argument");
+    *id = -1;
+    if (!(d->kinds & (RFS_PFB | RFS_DDC)) || (d->kinds & ~(RFS_PFB | RFS_DDC)))
+        return set_error(RF_EINVAL, "rfs_open_stream: kinds must be RFS_PFB and/or RFS_DDC");
+    if (d->max_buffer < 1) return set_error(RF_EINVAL, "rfs_open_stream: max_buffer must be >= 1");
+    const size_t fp = footprint_of(d);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if ((int)S->streams.size() >= S->max_streams)
+            return set_error(RF_EAGAIN, "rfs_open_stream: max_streams are open");
+        if (S->admitted + fp > S->budget)
+            return set_error(RF_EAGAIN, "rfs_open_stream: footprint exceeds the remaining device-memory budget");
+        S->admitted += fp;   // reserve
+    }
+    Stream *s = new (std::nothrow) Stream;
+    int rc = s ? RF_OK : set_error(RF_ENOMEM, "rfs_open_stream: host allocation");
+    if (!rc) {
+        s->kinds = d->kinds;
+        s->max_buffer = d->max_buffer;
+        s->nslots = d->out_slots > 0 ? d->out_slots : 1;
+        s->footprint = fp;
+        if (d->kinds & RFS_PFB) {
+            s->N = d->nchan;
+            s->M = d->ntaps;
+            rc = pfb_create(&s->pfb, d->nchan, d->ntaps, d->proto, RF_DFT_FFT_F32, d->max_buffer);
+            s->pfb_cap = slot_frames(d->nchan, d->ntaps, d->max_buffer);
+            for (int k = 0; !rc && k < s->nslots; ++k) {
+                float *p = nullptr;
+                if (hipMalloc((void **)&p, s->pfb_cap * d->nchan * 8) != hipSuccess)
+                    rc = set_error(RF_ENOMEM, "rfs_open_stream: output slot allocation");
+                else
+                    s->pfb_slot.push_back(p);
+            }
+        }
+        if (!rc && (d->kinds & RFS_DDC)) {
+            s->ntones = d->ntones;
+            rc = ddc_create(&s->ddc, d->ntones, d->phase_inc, d->phase0, d->lpf_taps, d->lpf, d->decim,
+                            d->max_buffer);
+            s->ddc_ld = slot_outputs(d->lpf_taps, d->decim, d->max_buffer);
+            for (int k = 0; !rc && k < s->nslots; ++k) {
+                float *p = nullptr;
+                if (hipMalloc((void **)&p, (size_t)d->ntones * s->ddc_ld * 8) != hipSuccess)
+                    rc = set_error(RF_ENOMEM, "rfs_open_stream: output slot allocation");
+                else
+                    s->ddc_slot.push_back(p);
+            }
+        }
+        for (int k = 0; k < s->nslots; ++k) s->free_slots.push_back(s->nslots - 1 - k);
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (rc) {
+        S->admitted -= fp;
+        free_stream(s);
+        return rc;
+    }
+    s->id = S->next_id++;
+    S->streams[s->id] = s;
+    rebuild_classes(S);
+    S->st.bytes_admitted = S->admitted;
+    S->st.streams_open = (int)S->streams.size();
+    *id = s->id;
+    return RF_OK;
+}
+
+int rfs_submit(rfs_t S, int32_t id, const int16_t *iq_dev, uint64_t nsamples, uint64_t tag)
+{
+    if (!S) return set_error(RF_EINVAL, "rfs_submit: server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return set_error(RF_EDEVICE, S->fatal.empty() ? "rfs_submit: server stopped" : S->fatal.c_str());
+    auto it = S->streams.find(id);
+    if (it == S->streams.end() || it->second->closing) return set_error(RF_EINVAL, "rfs_submit: unknown stream");
+    Stream *s = it->second;
+    if (nsamples > s->max_buffer) return set_error(RF_EINVAL, "rfs_submit: nsamples exceeds the stream's max_buffer");
+    if (nsamples > 0 && (!iq_dev || ((uintptr_t)iq_dev & 3)))
+        return set_error(RF_EINVAL, "rfs_submit: iq_dev must be a non-NULL 4-byte aligned device pointer");
+    s->queue.push_back(Request{iq_dev, nsamples, tag, now_s()});
+    S->cv_work.notify_one();
+    return RF_OK;
+}
+
+int rfs_poll(rfs_t S, rfs_completion *out, int32_t max, int32_t *count, int32_t timeout_us)
+{
+    if (!S || !count || (max > 0 && !out)) return set_error(RF_EINVAL, "rfs_poll: NULL argument");
+    *count = 0;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->completions.empty() && timeout_us > 0)
+        S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return !S->completions.empty(); });
+    while (*count < max && !S->completions.empty()) {
+        out[(*count)++] = S->completions.front();
+        S->completions.pop_front();
+    }
+    if (*count == 0 && S->stop && !S->fatal.empty()) return set_error(RF_EDEVICE, S->fatal.c_str());
+    return RF_OK;
+}
+
+int rfs_release(rfs_t S, int32_t id, int32_t slot)
+{
+    if (!S) return set_error(RF_EINVAL, "rfs_release: server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->streams.find(id);
+    if (it == S->streams.end()) return set_error(RF_EINVAL, "rfs_release: unknown stream");
+    Stream *s = it->second;
+    if (slot < 0 || slot >= s->nslots ||
+        std::find(s->free_slots.begin(), s->free_slots.end(), slot) != s->free_slots.end())
+        return set_error(RF_EINVAL, "rfs_release: slot is not held");
+    s->free_slots.push_back(slot);
+    S->cv_work.notify_one();
+    return RF_OK;
+}
+
+int rfs_close_stream(rfs_t S, int32_t id)
+{
+    if (!S) return set_error(RF_EINVAL, "rfs_close_stream: server is NULL");
+    Stream *s = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->streams.find(id);
+        if (it == S->streams.end()) return set_error(RF_EINVAL, "rfs_close_stream: unknown stream");
+        if (!it->second->queue.empty() || it->second->inflight > 0)
+            return set_error(RF_EAGAIN, "rfs_close_stream: the stream has queued or running requests");
+        s = it->second;
+        S->streams.erase(it);
+        S->admitted -= s->footprint;
+        rebuild_classes(S);
+        S->st.bytes_admitted = S->admitted;
+        S->st.streams_open = (int)S->streams.size();
+    }
+    free_stream(s);
+    return RF_OK;
+}
+
+int rfs_get_stats(rfs_t S, rfs_stats *st)
+{
+    if (!S || !st) return set_error(RF_EINVAL, "rfs_get_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *st = S->st;
+    return RF_OK;
+}
+
+int rfs_destroy(rfs_t S)
+{
+    if (!S) return RF_OK;
+    if (S->thr.joinable()) {
+        S->stop = true;
+        S->cv_work.notify_all();
+        S->thr.join();
+    }
+    if (S->hs) (void)hipStreamSynchronize(S->hs);
+    for (auto &kv : S->streams) free_stream(kv.second);
+    for (int k = 0; k < 2; ++k) {
+        Blob &b = S->blobs[k];
+        if (b.exec) (void)hipGraphExecDestroy(b.exec);
+        if (b.graph) (void)hipGraphDestroy(b.graph);
+        if (b.host) (void)hipHostFree(b.host);
+        if (b.dev) (void)hipFree(b.dev);
+        if (b.ev) (void)hipEventDestroy(b.ev);
+    }
+    for (hipEvent_t e : S->fork_ev) (void)hipEventDestroy(e);
+    for (hipStream_t bs : S->branch) (void)hipStreamDestroy(bs);
+    if (S->hs) (void)hipStreamDestroy(S->hs);
+    delete S;
+    return RF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+"""Serving core (rfs_* C ABI): continuous batching of many streams onto grouped
+kernels, hipGraph replay, admission by device-memory footprint.
+
+Every stream's results in the mix must equal the results of the same stream
+processed alone with its own pfb_/ddc_ handle -- bit for bit, since the grouped
+kernels run the same per-frame and per-output arithmetic -- and match the FP64
+oracle within the path's tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import siggen
+from gpu_util import err_fs, f32, log, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _rf():
+    need_gpu()
+    import paper_1812_02200_amd as rf
+    return rf
+
+
+def small_mix(seed=7):
+    rng = np.random.default_rng(seed)
+    shapes = [(64, 4, 0), (256, 8, 10), (1024, 8, 0), (4096, 4, 300), (1024, 8, 1500), (256, 4, 0)]
+    specs = []
+    for N, M, nt in shapes:
+        ddc = None
+        if nt:
+            ddc = (siggen.random_words(rng, nt), siggen.random_words(rng, nt),
+                   siggen.ddc_lowpass(256, 400e3), 200)
+        specs.append(dict(N=N, M=M, h=siggen.pfb_prototype(N, M, "kaiser", 9.0), ddc=ddc))
+    sizes = [[int(2 ** rng.integers(10, 17)) for _ in range(5)] for _ in specs]
+    return specs, sizes
+
+
+def reference_alone(rf, torch, spec, bufs):
+    """The same stream through its own plain handles."""
+    p = rf.Pfb(spec["N"], spec["M"], spec["h"], max_samples_per_call=1 << 16)
+    d = None
+    if spec["ddc"] is not None:
+        w, p0, lpf, D = spec["ddc"]
+        d = rf.Ddc(w, lpf, D, p0, max_samples_per_call=1 << 16)
+    out = []
+    for b in bufs:
+        rec = {"pfb": p.process(b).cpu().numpy()}
+        if d is not None:
+            rec["ddc"] = d.process(b).cpu().numpy()
+        out.append(rec)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("mode", ["sequential", "batched", "graph"])
+def test_serve_mix_equals_alone_bit_exact(mode):
+    rf = _rf()
+    import torch
+
+    from paper_1812_02200_amd import serve
+    specs, sizes = small_mix()
+    pool_n = 1 << 20
+    pool = siggen.iq_torch(siggen.StreamSpec(9, siggen.pfb_small().stream.tones, 700.0), 0, pool_n)
+    # build an arrival list: all buffers at t = 0, stream-interleaved
+    mix_specs, arrivals = [], []
+    rng = np.random.default_rng(3)
+    for s, sp in enumerate(specs):
+        off = int(rng.integers(0, pool_n // 2))
+        mix_specs.append(serve.StreamSpecMix(sp["N"], sp["M"], sp["h"], sp["ddc"], off, 1 << 16))
+        pos = off
+        for n in sizes[s]:
+            arrivals.append(serve.Arrival(0.0, s, n, pos))
+            pos += n
+    m = {"sequential": rf.RFS_MODE_SEQUENTIAL, "batched": rf.RFS_MODE_BATCHED, "graph": rf.RFS_MODE_GRAPH}[mode]
+    log("serve %s: %d streams, %d requests" % (mode, len(specs), len(arrivals)))
+    res = serve.run(mix_specs, arrivals, pool, m, budget=8 << 30, realtime=False, collect=True)
+    assert res["requests"] == len(arrivals)
+    for s, sp in enumerate(specs):
+        bufs = [pool[2 * a.pool_start: 2 * (a.pool_start + a.nsamples)] for a in arrivals if a.stream == s]
+        ref = reference_alone(rf, torch, sp, bufs)
+        got = res["outputs"][s]
+        assert len(got) == len(ref)
+        for g, r in zip(got, ref):
+            assert g["pfb"].shape == r["pfb"].shape
+            assert np.array_equal(g["pfb"].view(np.uint64), r["pfb"].view(np.uint64)), (mode, s)
+            if sp["ddc"] is not None:
+                assert g["ddc"].shape == r["ddc"].shape
+                assert np.array_equal(g["ddc"].view(np.uint64), r["ddc"].view(np.uint64)), (mode, s)
+    # one stream against the oracle as well
+    s = 3
+    sp = specs[s]
+    iq = np.concatenate([pool[2 * a.pool_start: 2 * (a.pool_start + a.nsamples)].cpu().numpy()
+                         for a in arrivals if a.stream == s])
+    y = np.concatenate([g["pfb"] for g in res["outputs"][s]])
+    ref = oracle.pfb(f32(sp["h"]), sp["N"], sp["M"], iq=iq)
+    assert y.shape == ref.shape and err_fs(y, ref, sp["h"].sum()) <= 1e-5
+    w, p0, lpf, D = sp["ddc"]
+    yd = np.concatenate([g["ddc"] for g in res["outputs"][s]], axis=1)
+    refd = oracle.ddc(w, p0, f32(lpf), D, iq=iq)
+    assert yd.shape == refd.shape and err_fs(yd, refd, lpf.sum()) <= 1e-5
+
+
+def test_serve_admission_by_footprint_and_close():
+    rf = _rf()
+    import torch
+    h = siggen.pfb_prototype(1024, 8)
+    d1, k1 = rf.Server.make_desc(pfb=(1024, 8, h), max_buffer=1 << 20, out_slots=1)
+    fp = rf.Server.footprint(d1)
+    srv = rf.Server(int(fp * 1.5), rf.RFS_MODE_GRAPH, 8)
+    a = srv.open_stream(d1, k1)
+    d2, k2 = rf.Server.make_desc(pfb=(1024, 8, h), max_buffer=1 << 20, out_slots=1)
+    assert srv.try_open_stream(d2, k2) is None            # does not fit: RF_EAGAIN
+    assert srv.stats()["bytes_admitted"] == fp
+    # with one output slot, a second request stays queued until the first is released
+    buf = siggen.iq_torch(siggen.StreamSpec(11, siggen.pfb_small().stream.tones, 500.0), 0, 1 << 16)
+    srv.submit(a, buf.data_ptr(), 1 << 15, 1)
+    srv.submit(a, buf.data_ptr() + 4 * (1 << 15), 1 << 15, 2)
+    got = []
+    while not got:
+        got = srv.poll(8, 100000)
+    assert [c["tag"] for c in got] == [1]
+    with pytest.raises(rf.RfError) as ei:
+        srv.close_stream(a)
+    assert ei.value.status == rf.RF_EAGAIN
+    srv.release(a, got[0]["slot"])
+    got = []
+    while not got:
+        got = srv.poll(8, 100000)
+    assert [c["tag"] for c in got] == [2]
+    assert got[0]["pfb_frames"] == ((1 << 16) - 8192) // 1024 + 1 - (((1 << 15) - 8192) // 1024 + 1)
+    srv.release(a, got[0]["slot"])
+    srv.close_stream(a)
+    b = srv.open_stream(d2, k2)                            # now it fits
+    assert b != a
+    with pytest.raises(rf.RfError):
+        srv.submit(b, buf.data_ptr(), (1 << 20) + 1, 0)    # larger than max_buffer
+    srv.close()
+    torch.cuda.synchronize()
