@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "pfb", "ddc", "precision"])
+    ap.add_argument("--workload", default="all", choices=["all", "pfb", "ddc", "precision", "serving"])
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget per oracle baseline sample")
@@ -57,6 +58,8 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
     fpb = w.buffer // w.N                           # frames per buffer in steady state
     out = torch.empty((nbuf, fpb, w.N), dtype=torch.complex64, device="cuda")
     p = rf.Pfb(w.N, w.M, w.h, max_samples_per_call=w.buffer)
+    tuned = p.tune(w.buffer)          # launch shape chosen by the autotuner (setup, untimed)
+    log("pfb tuned: %.1f us/launch, run_len=%d variant=%d" % tuned)
     s = torch.cuda.current_stream()
     sh = s.cuda_stream
     base_in, base_out = d.data_ptr(), out.data_ptr()
@@ -91,6 +94,7 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
         "wall_ms_per_step": wall * 1e3 / steps,
         "frames_per_step": (frames[0] - f0) / steps,
         "kernel_us": kern_s * 1e6,
+        "tuned": {"run_len": tuned[1], "variant": tuned[2], "us_per_launch": tuned[0]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "per_launch": "12 B x 2^24 samples = %.1f MB" % (bytes_per_launch / 1e6)},
@@ -127,6 +131,8 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     ld = w.buffer // w.D + 2
     out = torch.empty((nbuf, w.words.size, ld), dtype=torch.complex64, device="cuda")
     dd = rf.Ddc(w.words, w.h, w.D, w.phase0, max_samples_per_call=w.buffer)
+    dtuned = dd.tune(w.buffer)
+    log("ddc tuned: %.1f us/launch, grid=%d" % dtuned)
     s = torch.cuda.current_stream()
     sh = s.cuda_stream
     base_in, base_out = d.data_ptr(), out.data_ptr()
@@ -159,6 +165,7 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
         "ms_per_step": ms / steps,
         "kernel_us": kern_s * 1e6,
         "outputs_per_tone_per_step": outs / steps,
+        "tuned": {"grid": dtuned[1], "us_per_launch": dtuned[0]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TF,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TF, "traffic": None,
                      "per_launch": "8 flop x 1024 taps x 1000 tones x %.1f outputs" % (outs / launches)},
@@ -206,12 +213,12 @@ def bench_precision(rf, torch, siggen, oracle, steps, warmup):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         tot = 0.0
         for _ in range(steps):
+            p.reset()
             e0.record(s)
             p.process_ptr(d.data_ptr(), w.nsamples, out.data_ptr(), nf, sh)
             e1.record(s)
             torch.cuda.synchronize()
             tot += e0.elapsed_time(e1)
-            p.reset()
         ms = tot / steps
         once()
         torch.cuda.synchronize()
@@ -236,10 +243,37 @@ def bench_precision(rf, torch, siggen, oracle, steps, warmup):
     return res
 
 
+# --------------------------------------------------------------- serving
+
+def bench_serving(rf, torch, seconds):
+    """16-stream mix (Poisson arrivals, 1.6 Gs/s offered): latency and throughput per mode."""
+    from paper_1812_02200_amd import serve
+    specs, arrivals = serve.build_mix(duration_s=seconds)
+    log("serving: %d streams, %d buffers over %.1f s" % (len(specs), len(arrivals), seconds))
+    pool = serve.make_pool()
+    torch.cuda.synchronize()
+    res = {"config": {"workload": "16 streams, N in {64,256,1024,4096}, M in {4,8}, 8 with DDC "
+                                  "banks of 10-2000 tones (T=1024, D=1000), buffers 2^16..2^24, "
+                                  "Poisson arrivals at 1.6 Gs/s", "seconds": seconds,
+                      "buffers": len(arrivals)}}
+    modes = (("graph", rf.RFS_MODE_GRAPH), ("batched", rf.RFS_MODE_BATCHED),
+             ("sequential", rf.RFS_MODE_SEQUENTIAL))
+    for name, m in modes:
+        r = serve.run(specs, arrivals, pool, m, realtime=True)
+        res[name] = {"latency_ms": r["latency_ms"], "msamples_per_s": r["msamples_per_s"],
+                     "batches": r["batches"]}
+        log("serving %s: p50 %.2f ms p99 %.2f ms" % (name, r["latency_ms"]["p50"], r["latency_ms"]["p99"]))
+    for name, m in modes:
+        r = serve.run(specs, arrivals, pool, m, realtime=False)
+        res[name]["saturation_msamples_per_s"] = r["msamples_per_s"]
+        log("serving %s saturation: %.0f Msamples/s" % (name, r["msamples_per_s"]))
+    return res
+
+
 def cpu_ddc(oracle, w, d, budget_s):
     """The FP64 oracle on the first outputs of every tone, sized to ~budget_s of CPU work."""
-    iq = d[: 2 * (w.buffer)].cpu().numpy()
-    nout = oracle.ddc_noutputs(w.buffer, w.h.size, w.D)
+    iq = d.cpu().numpy()
+    nout = oracle.ddc_noutputs(w.nsamples, w.h.size, w.D)
     ntones = w.words.size
 
     def run(k):
@@ -297,6 +331,9 @@ def main():
     if a.workload in ("all", "precision"):
         import oracle
         rec["precision"] = bench_precision(rf, torch, siggen, oracle, max(1, min(a.steps, 5)), 1)
+    if a.workload in ("all", "serving"):
+        rec["serving"] = bench_serving(rf, torch, a.serve_seconds)
+        rec["p99_buffer_latency_ms"] = rec["serving"]["graph"]["latency_ms"]["p99"]
     if not a.no_cpu_baseline:
         import oracle
         if "pfb" in keep:

@@ -182,6 +182,25 @@ int ddc_set_state(rf_ddc_t ddc, const void *blob, size_t size);
 int ddc_reset(rf_ddc_t ddc);
 int ddc_destroy(rf_ddc_t ddc);
 
+/* ============================================================ Autotuner
+ *
+ * The paper's handling thread tunes the GPU kernels at run time (Sec. III).
+ * pfb_tune / ddc_tune time the candidate launch configurations of a handle
+ * for buffers of `nsamples` samples on `hip_stream` -- frames per work-group
+ * run and kernel variant for the PFB, persistent grid size for the DDC -- on
+ * scratch buffers allocated and freed inside the call (the stream state is
+ * not touched; the call waits for the handle's pending work first), keep the
+ * fastest in the handle and append it to a text cache (RFCHAN_TUNE_CACHE, or
+ * $HOME/.cache/rfchan_tune.txt).  *_apply_tuned loads a cached choice for a
+ * buffer size (RF_EAGAIN if none is cached).  best_us (may be NULL) receives
+ * the chosen configuration's time per launch. */
+int pfb_tune(rf_pfb_t pfb, uint64_t nsamples, void *hip_stream, double *best_us);
+int pfb_apply_tuned(rf_pfb_t pfb, uint64_t nsamples);
+int pfb_tuned_config(rf_pfb_t pfb, int32_t *run_len, int32_t *variant);
+int ddc_tune(rf_ddc_t ddc, uint64_t nsamples, void *hip_stream, double *best_us);
+int ddc_apply_tuned(rf_ddc_t ddc, uint64_t nsamples);
+int ddc_tuned_config(rf_ddc_t ddc, int32_t *grid);
+
 /* ============================================================ Serving
  *
  * A server multiplexes many readout streams onto one GPU, the way the paper's

@@ -85,6 +85,12 @@ SIGNATURES = {
     "ddc_set_state": (ctypes.c_int, [_P, _P, _SZ]),
     "ddc_reset": (ctypes.c_int, [_P]),
     "ddc_destroy": (ctypes.c_int, [_P]),
+    "pfb_tune": (ctypes.c_int, [_P, _U64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "pfb_apply_tuned": (ctypes.c_int, [_P, _U64]),
+    "pfb_tuned_config": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "ddc_tune": (ctypes.c_int, [_P, _U64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "ddc_apply_tuned": (ctypes.c_int, [_P, _U64]),
+    "ddc_tuned_config": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     "rfs_create": (ctypes.c_int, [ctypes.POINTER(_P), _U64, _I32, _I32]),
     "rfs_stream_footprint": (_U64, [ctypes.POINTER(StreamDesc)]),
     "rfs_open_stream": (ctypes.c_int, [_P, ctypes.POINTER(StreamDesc), ctypes.POINTER(_I32)]),
@@ -203,6 +209,22 @@ class Pfb:
                                 ctypes.byref(got), stream_handle), "pfb_process")
         return got.value
 
+    def tune(self, nsamples: int, stream=None):
+        """Autotune the launch configuration for buffers of `nsamples`; returns
+        (microseconds per launch, run_len, variant)."""
+        us = ctypes.c_double(0)
+        check(lib().pfb_tune(self._h, int(nsamples), _stream_handle(stream), ctypes.byref(us)), "pfb_tune")
+        rl, var = _I32(), _I32()
+        check(lib().pfb_tuned_config(self._h, ctypes.byref(rl), ctypes.byref(var)), "pfb_tuned_config")
+        return us.value, rl.value, var.value
+
+    def apply_tuned(self, nsamples: int) -> bool:
+        st = lib().pfb_apply_tuned(self._h, int(nsamples))
+        if st == RF_EAGAIN:
+            return False
+        check(st, "pfb_apply_tuned")
+        return True
+
     def counters(self):
         a, b, c = _U64(), _U64(), _U64()
         check(lib().pfb_counters(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
@@ -280,6 +302,21 @@ class Ddc:
         check(lib().ddc_process(self._h, iq_ptr, nsamples, out_ptr, ld, ctypes.byref(got),
                                 stream_handle), "ddc_process")
         return got.value
+
+    def tune(self, nsamples: int, stream=None):
+        """Autotune the persistent grid for buffers of `nsamples`; returns (us, grid)."""
+        us = ctypes.c_double(0)
+        check(lib().ddc_tune(self._h, int(nsamples), _stream_handle(stream), ctypes.byref(us)), "ddc_tune")
+        g = _I32()
+        check(lib().ddc_tuned_config(self._h, ctypes.byref(g)), "ddc_tuned_config")
+        return us.value, g.value
+
+    def apply_tuned(self, nsamples: int) -> bool:
+        st = lib().ddc_apply_tuned(self._h, int(nsamples))
+        if st == RF_EAGAIN:
+            return False
+        check(st, "ddc_apply_tuned")
+        return True
 
     def phase(self):
         import numpy as np

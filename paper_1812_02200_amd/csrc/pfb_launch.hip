@@ -69,6 +69,26 @@ hipError_t launch_pfb(const PfbLaunch &a, hipStream_t s)
     }
 }
 
+// Pseudo-random 14-bit I/Q words for tuning buffers (a data-independent
+// kernel still runs at different clocks on all-zero and on busy data).
+__global__ void fill_iq_kernel(uint32_t *p, uint64_t n, uint32_t seed)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+        x ^= x >> 15;
+        x *= 2246822519u;
+        x ^= x >> 13;
+        const uint32_t I = (x & 0x3fffu) - 0x2000u, Q = ((x >> 16) & 0x3fffu) - 0x2000u;
+        p[i] = (I & 0xffffu) | (Q << 16);
+    }
+}
+
+hipError_t fill_iq(uint32_t *p, uint64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_iq_kernel, dim3(1024), dim3(256), 0, s, p, n, 0x9e3779b9u);
+    return hipGetLastError();
+}
+
 int64_t pfb_launch_wgs(const PfbLaunch &a)
 {
     switch (a.N) {

@@ -70,6 +70,9 @@ hipError_t launch_pfb_group(int N, int M, const GroupHeader *hdr, const PfbItem 
                             hipStream_t s);
 int pfb_group_wg_size(int N);
 
+// Fill n packed I/Q words with pseudo-random 14-bit values (tuning scratch).
+hipError_t fill_iq(uint32_t *p, uint64_t n, hipStream_t s);
+
 // Twiddle table size (float pairs) for an N-point plan.
 int pfb_twiddle_count(int N);
 // Fill the twiddle table (host memory, float pairs) for an N-point plan.

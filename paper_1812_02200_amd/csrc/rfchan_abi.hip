@@ -11,6 +11,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <sys/stat.h>
+
 #include <new>
 #include <string>
 
@@ -821,6 +823,309 @@ int ddc_destroy(rf_ddc_t p)
         ddc_free(p);
     }
     return rc;
+}
+
+}  // extern "C"
+
+// ================================================================ autotuner
+//
+// Candidate launch configurations are timed with HIP events on scratch
+// buffers (the handle's history, phase and counters are not touched); the
+// fastest is kept in the handle and appended to a plain-text cache
+// (RFCHAN_TUNE_CACHE, default $HOME/.cache/rfchan_tune.txt), one line per
+// "kind arch key... choice... microseconds", which *_create consults.
+
+namespace {
+
+// Bytes of scratch traffic the tuner spreads its launches over (twice the
+// MI355X's 256 MB last-level cache), so timings reflect HBM, not cache.
+constexpr uint64_t kTuneFootprint = 512ull << 20;
+
+std::string tune_cache_path()
+{
+    const char *p = getenv("RFCHAN_TUNE_CACHE");
+    if (p && *p) return p;
+    const char *h = getenv("HOME");
+    return std::string(h ? h : ".") + "/.cache/rfchan_tune.txt";
+}
+
+std::string device_arch(int dev)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Last cache line matching the key; returns the numbers after the key.
+bool tune_lookup(const std::string &key, long *v, int nv)
+{
+    FILE *f = fopen(tune_cache_path().c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        if (strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
+        const char *q = line + key.size();
+        long tmp[8];
+        int got = 0;
+        for (; got < nv && got < 8; ++got) {
+            char *end = nullptr;
+            tmp[got] = strtol(q, &end, 10);
+            if (end == q) break;
+            q = end;
+        }
+        if (got == nv) {
+            for (int i = 0; i < nv; ++i) v[i] = tmp[i];
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void tune_store(const std::string &key, const long *v, int nv, double us)
+{
+    std::string path = tune_cache_path();
+    size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);  // best effort
+    FILE *f = fopen(path.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "%s", key.c_str());
+    for (int i = 0; i < nv; ++i) fprintf(f, " %ld", v[i]);
+    fprintf(f, " %.3f\n", us);
+    fclose(f);
+}
+
+std::string pfb_key(const rf_pfb *p, uint64_t n)
+{
+    char b[128];
+    snprintf(b, sizeof b, "pfb %s %d %d %d %llu", device_arch(p->device).c_str(), p->N, p->M, p->mode,
+             (unsigned long long)n);
+    return b;
+}
+
+std::string ddc_key(const rf_ddc *p, uint64_t n)
+{
+    char b[128];
+    snprintf(b, sizeof b, "ddc %s %d %d %d %llu", device_arch(p->device).c_str(), p->ntones, p->T, p->D,
+             (unsigned long long)n);
+    return b;
+}
+
+// Average duration (us) of `reps` launches of `fn` on stream s.
+template <typename Fn>
+int time_launches(hipStream_t s, int reps, Fn fn, double *us)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    e = fn();   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "tuning launch");
+    *us = ms * 1e3 / reps;
+    return RF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
+{
+    if (!p || nsamples < (uint64_t)p->N * p->M || nsamples > p->max_samples)
+        return fail(RF_EINVAL, "pfb_tune: need a handle and N*M <= nsamples <= max_samples_per_call");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = p->order.sync();
+    if (rc) return rc;
+    const uint64_t F = (nsamples - (uint64_t)p->N * p->M) / p->N + 1;
+    // Rotate over enough scratch copies that their traffic exceeds the 256 MB
+    // last-level cache, as a long stream does.
+    const uint64_t per = nsamples * 4 + F * p->N * 8;
+    int copies = (int)((kTuneFootprint + per - 1) / per);
+    if (copies < 1) copies = 1;
+    if (copies > 32) copies = 32;
+    uint32_t *in = nullptr, *hist = nullptr;
+    float *out = nullptr;
+    if ((rc = dev_alloc(&in, nsamples * copies, "tune input")) ||
+        (rc = dev_alloc(&hist, (size_t)p->N * p->M, "tune history")) ||
+        (rc = dev_alloc(&out, 2 * F * p->N * copies, "tune output"))) {
+        (void)hipFree(in);
+        (void)hipFree(hist);
+        return rc;
+    }
+    (void)rfk::fill_iq(in, nsamples * copies, s);
+    rfk::PfbLaunch a{};
+    a.vs.hist = hist;
+    a.vs.H = 0;
+    a.vs.n = (int64_t)nsamples;
+    a.hist_out = hist;
+    a.keep_from = (int64_t)F * p->N;
+    a.keep_len = (int64_t)nsamples - a.keep_from;
+    a.taps = p->d_taps;
+    a.tw = p->d_tw;
+    a.F = (int64_t)F;
+    a.N = p->N;
+    a.M = p->M;
+    static const int rls[] = {8, 12, 16, 20, 24, 32, 48, 64};
+    const int nvar = (p->mode == RF_DFT_FFT_F32 && p->N == 1024 && p->M == 8) ? 2 : 1;
+    double best = 1e30;
+    int best_rl = 0, best_var = 0;
+    int k = 0;
+    for (int rl : rls) {
+        for (int var = 0; var < nvar; ++var) {
+            a.run_len = rl;
+            a.variant = var;
+            double us = 0;
+            rc = time_launches(s, 2 * copies, [&]() {
+                a.vs.in = in + (size_t)(k % copies) * nsamples;
+                a.out = out + (size_t)(k % copies) * 2 * F * p->N;
+                ++k;
+                return p->mode == RF_DFT_FFT_F32
+                           ? rfk::launch_pfb(a, s)
+                           : rfk::launch_pfb_mfma(a, p->mode == RF_DFT_MFMA_BF16X2 ? rfk::RF_PREC_BF16 : rfk::RF_PREC_F16, s);
+            }, &us);
+            if (rc) break;
+            if (us < best) {
+                best = us;
+                best_rl = rl;
+                best_var = var;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(in);
+    (void)hipFree(hist);
+    (void)hipFree(out);
+    if (rc) return rc;
+    p->run_len = best_rl;
+    p->variant = best_var;
+    const long v[2] = {best_rl, best_var};
+    tune_store(pfb_key(p, nsamples), v, 2, best);
+    if (best_us) *best_us = best;
+    return RF_OK;
+}
+
+int pfb_tuned_config(rf_pfb_t p, int32_t *run_len, int32_t *variant)
+{
+    if (!p) return fail(RF_EINVAL, "pfb_tuned_config: handle is NULL");
+    if (run_len) *run_len = p->run_len;
+    if (variant) *variant = p->variant;
+    return RF_OK;
+}
+
+int ddc_tune(rf_ddc_t p, uint64_t nsamples, void *hip_stream, double *best_us)
+{
+    if (!p || nsamples < (uint64_t)p->T || nsamples > p->max_samples)
+        return fail(RF_EINVAL, "ddc_tune: need a handle and T <= nsamples <= max_samples_per_call");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = p->order.sync();
+    if (rc) return rc;
+    const uint64_t nout = (nsamples - p->T) / p->D + 1;
+    uint32_t *in = nullptr, *hist = nullptr;
+    float *out = nullptr;
+    uint64_t *phase = nullptr;
+    if ((rc = dev_alloc(&in, nsamples, "tune input")) || (rc = dev_alloc(&hist, (size_t)p->T, "tune history")) ||
+        (rc = dev_alloc(&out, 2 * nout * p->ntones, "tune output")) ||
+        (rc = dev_alloc(&phase, p->ntones, "tune phase"))) {
+        (void)hipFree(in);
+        (void)hipFree(hist);
+        (void)hipFree(out);
+        return rc;
+    }
+    (void)rfk::fill_iq(in, nsamples, s);
+    rfk::DdcLaunch a{};
+    a.vs.hist = hist;
+    a.vs.in = in;
+    a.vs.H = 0;
+    a.vs.n = (int64_t)nsamples;
+    a.hist_out = hist;
+    a.keep_from = (int64_t)(nout * p->D);
+    a.keep_len = (int64_t)nsamples - a.keep_from;
+    if (a.keep_len < 0) a.keep_len = 0;
+    a.out = out;
+    a.ld = (int64_t)nout;
+    a.wrev = p->d_wrev;
+    a.inc = p->d_inc;
+    a.phi0 = p->d_phi0;
+    a.sintab = p->d_tab;
+    a.base_abs = 0;
+    a.nout = (int64_t)nout;
+    a.phase_out = phase;
+    a.phase_at = nsamples;
+    a.T = p->T;
+    a.D = p->D;
+    a.ntones = p->ntones;
+    const int grids[] = {p->cus / 2, p->cus, 2 * p->cus, 4 * p->cus};
+    double best = 1e30;
+    int best_grid = p->cus;
+    for (int g : grids) {
+        if (g < 1) continue;
+        a.grid = g;
+        double us = 0;
+        rc = time_launches(s, 3, [&]() { return rfk::launch_ddc(a, s); }, &us);
+        if (rc) break;
+        if (us < best) {
+            best = us;
+            best_grid = g;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(in);
+    (void)hipFree(hist);
+    (void)hipFree(out);
+    (void)hipFree(phase);
+    if (rc) return rc;
+    p->grid = best_grid;
+    const long v[1] = {best_grid};
+    tune_store(ddc_key(p, nsamples), v, 1, best);
+    if (best_us) *best_us = best;
+    return RF_OK;
+}
+
+int ddc_tuned_config(rf_ddc_t p, int32_t *grid)
+{
+    if (!p) return fail(RF_EINVAL, "ddc_tuned_config: handle is NULL");
+    if (grid) *grid = p->grid;
+    return RF_OK;
+}
+
+int pfb_apply_tuned(rf_pfb_t p, uint64_t nsamples)
+{
+    if (!p) return fail(RF_EINVAL, "pfb_apply_tuned: handle is NULL");
+    long v[2];
+    if (!tune_lookup(pfb_key(p, nsamples), v, 2)) return RF_EAGAIN;
+    if (v[0] < 4 || v[0] % 4) return fail(RF_EINVAL, "pfb_apply_tuned: corrupt cache entry");
+    p->run_len = (int)v[0];
+    p->variant = (int)v[1];
+    return RF_OK;
+}
+
+int ddc_apply_tuned(rf_ddc_t p, uint64_t nsamples)
+{
+    if (!p) return fail(RF_EINVAL, "ddc_apply_tuned: handle is NULL");
+    long v[1];
+    if (!tune_lookup(ddc_key(p, nsamples), v, 1)) return RF_EAGAIN;
+    if (v[0] < 1) return fail(RF_EINVAL, "ddc_apply_tuned: corrupt cache entry");
+    p->grid = (int)v[0];
+    return RF_OK;
 }
 
 }  // extern "C"

@@ -186,6 +186,25 @@ def test_ddc_on_grid_tone_is_dc():
     assert np.max(np.abs(y - want)) < 1.0
 
 
+def test_ddc_tune_keeps_results_bit_exact(tmp_path, monkeypatch):
+    monkeypatch.setenv("RFCHAN_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    rf = _rf()
+    import torch
+    rng = np.random.default_rng(59)
+    words = siggen.random_words(rng, 700)
+    h = siggen.ddc_lowpass(512, 1e6)
+    n = 60000
+    iq = siggen.StreamSpec(59, siggen.ToneSet(words[:10], np.full(10, 40.0), np.zeros(10)), 300.0).iq(0, n)
+    d = to_dev(iq)
+    base = run_ddc(rf.Ddc(words, h, 400, max_samples_per_call=n), d, [n], torch)
+    dd = rf.Ddc(words, h, 400, max_samples_per_call=n)
+    us, grid = dd.tune(n)
+    assert us > 0 and grid >= 1
+    got = run_ddc(dd, d, [n], torch)
+    assert np.array_equal(got.view(np.uint64), base.view(np.uint64))
+    assert rf.Ddc(words, h, 400, max_samples_per_call=n).apply_tuned(n)
+
+
 @pytest.mark.slow
 def test_ddc_bank_full_size_sampled():
     """1000 tones, T=1024 Blackman, D=1000, 2^27 samples in 2^23 buffers -> 1000 x 134217.

@@ -195,6 +195,28 @@ def test_pfb_two_streams_are_ordered():
     assert np.array_equal(got.view(np.uint64), whole.view(np.uint64))
 
 
+def test_pfb_tune_keeps_results_bit_exact(tmp_path, monkeypatch):
+    """Tuning changes only the launch shape: every frame is computed the same way."""
+    monkeypatch.setenv("RFCHAN_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    rf = _rf()
+    import torch
+    N, M = 1024, 8
+    h = siggen.pfb_prototype(N, M, "kaiser")
+    n = N * 2000 + 11
+    iq = siggen.StreamSpec(31, siggen.pfb_small().stream.tones, 400.0).iq(0, n)
+    d = to_dev(iq)
+    base = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, [n], torch)
+    p = rf.Pfb(N, M, h, max_samples_per_call=n)
+    us, rl, var = p.tune(n)
+    log("tuned: %.1f us, run_len=%d variant=%d" % (us, rl, var))
+    assert us > 0 and rl % 4 == 0 and var in (0, 1)
+    got = run_pfb(p, d, [n], torch)
+    assert np.array_equal(got.view(np.uint64), base.view(np.uint64))
+    q = rf.Pfb(N, M, h, max_samples_per_call=n)
+    assert q.apply_tuned(n) and not q.apply_tuned(n + 1)
+    assert (tmp_path / "tune.txt").read_text().startswith("pfb gfx950 1024 8 0 %d" % n)
+
+
 @pytest.mark.slow
 def test_pfb_production_full_size_sampled():
     """N=1024, M=8, Kaiser(9): 2^28 samples in 16 buffers of 2^24 -> 262137 frames.
