@@ -9,79 +9,105 @@
 // every lane (one tone each) runs a single complex multiply-accumulate per
 // sample against its own oscillator:
 //     y_t[n] = sum_j u_n[j] conj(c_t[nD + j]).
-// The oscillator is an exact 64-bit integer accumulator.  Its table lookup
-// uses a half-wave sine table in LDS (2^15 FP32 values, 128 KiB):
-//     sin(2 pi i/2^16) = +-S[i mod 2^15]   (sign = bit 15 of i),
-//     cos(2 pi i/2^16) = sin(2 pi (i + 2^14)/2^16),
-// which is bit-identical to the full 2^16-entry table because every entry is
-// the same quarter-wave value q[j] = fp32(sin(pi j/2^15)) with a sign.
-// The input is read from HBM once per output for all tones of a tile.
+// The oscillator is an exact 64-bit integer accumulator.  Its 16-bit table
+// index i = phi >> 48 splits into a quadrant g = i >> 14 and an offset
+// r = i mod 2^14, and Tab[i] = (cos, sin)(2 pi i / 2^16) = (j)^g P[r] with
+// the quarter-wave pair P[r] = (q[2^14 - r], q[r]), q[r] = fp32(sin(pi r/2^15)).
+// So conj(Tab[i]) = (-j)^g conj(P[r]), and the quadrant turn is moved onto
+// the input: LDS holds the four copies U_g[j] = (-j)^g u[j] (exact sign and
+// swap operations), and each sample costs one (cos, sin) pair read from a
+// 128 KiB table in LDS, one read of the quadrant's copy, and four FMAs.  The
+// products are the same FP32 products as with the full 2^16-entry table.
+//
+// Each work-group owns a contiguous range of outputs of one tone chunk, so a
+// tone's consecutive outputs are written by one work-group (whole cache
+// sectors reach HBM, not 8-byte fragments from different L2 slices).
 #include "fft_device.hpp"
 #include "rf_internal.hpp"
 
 namespace rfk {
+
+constexpr int kUChunk = 1024;                    // taps per LDS pass
+constexpr int kPairs = kSinTabLen / 2;           // 2^14 (cos, sin) pairs
+constexpr int kDdcLds = 4 * kUChunk + kPairs;    // float2 entries: 160 KiB
 
 __device__ __forceinline__ uint32_t dvload(const VStream &vs, int64_t v)
 {
     return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
 }
 
-__device__ __forceinline__ float with_sign_of(uint32_t signsrc, float mag)
-{
-    // mag >= 0: OR in bit 31 of signsrc
-    return __uint_as_float((signsrc & 0x80000000u) | __float_as_uint(mag));
-}
-
 // One work unit: output o of tone chunk tc (tones tc*WG .. tc*WG+WG-1).
-// `u` is the work-group's LDS buffer for the tap-weighted input, `stab` the
-// half-wave sine table already in LDS.  Contains two barriers; every thread of
-// the work-group must call it.
+// `lds` holds the four rotated input copies (first 4*kUChunk entries) and the
+// pair table (loaded by the caller).  Contains two barriers per tap chunk;
+// every thread of the work-group must call it.
 template <int WG>
-__device__ __forceinline__ void ddc_unit(const DdcLaunch &a, int tc, int64_t o, const float *stab, cf *u)
+__device__ __forceinline__ void ddc_unit(const DdcLaunch &a, int tc, int64_t o, float2 *lds)
 {
     const int tid = threadIdx.x;
     const VStream &vs = a.vs;
     const int T = a.T;
-    __syncthreads();  // previous unit's readers are done with u (and the table is loaded)
     const int64_t v0 = o * a.D;
-    for (int j = tid; j < T; j += WG) {
-        const uint32_t w = dvload(vs, v0 + j);
-        const cf x = {(float)(int16_t)(w & 0xffffu), (float)(int16_t)(w >> 16)};
-        const float h = a.wrev[j];
-        u[j] = {h * x.x, h * x.y};
-    }
-    __syncthreads();
     const int t = tc * WG + tid;
-    if (t < a.ntones) {
-        const uint64_t inc = a.inc[t];
-        uint64_t ph = a.phi0[t] + (a.base_abs + (uint64_t)v0) * inc;
-        // four interleaved partial sums (j mod 4): independent FMA chains
-        float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
-        auto mac = [&](int q, int j) {
-            const uint32_t hi = (uint32_t)(ph >> 32);
-            const uint32_t hc = hi + 0x40000000u;  // +quarter turn: cos = sin(. + pi/2)
-            const float s = with_sign_of(hi, stab[(hi >> 16) & 0x7fffu]);
-            const float c = with_sign_of(hc, stab[(hc >> 16) & 0x7fffu]);
-            const cf uu = u[j];
-            // u * conj(c + i s)
-            ar[q] = __builtin_fmaf(uu.x, c, ar[q]);
-            ar[q] = __builtin_fmaf(uu.y, s, ar[q]);
-            ai[q] = __builtin_fmaf(uu.y, c, ai[q]);
-            ai[q] = __builtin_fmaf(-uu.x, s, ai[q]);
-            ph += inc;
-        };
-        const int T4 = T & ~3;
-#pragma unroll 2
-        for (int j = 0; j < T4; j += 4) {
-            mac(0, j);
-            mac(1, j + 1);
-            mac(2, j + 2);
-            mac(3, j + 3);
+    const bool live = t < a.ntones;
+    uint64_t inc = 0, ph = 0;
+    if (live) {
+        inc = a.inc[t];
+        ph = a.phi0[t] + (a.base_abs + (uint64_t)v0) * inc;
+    }
+    // four interleaved partial sums (j mod 4): independent FMA chains
+    float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+    const char *ub = reinterpret_cast<const char *>(lds);
+    const char *pt = reinterpret_cast<const char *>(lds + 4 * kUChunk);
+    for (int c0 = 0; c0 < T; c0 += kUChunk) {
+        const int len = min(kUChunk, T - c0);
+        __syncthreads();  // previous readers are done with the copies (and the table is loaded)
+        for (int j = tid; j < len; j += WG) {
+            const uint32_t w = dvload(vs, v0 + c0 + j);
+            const float h = a.wrev[c0 + j];
+            const float ux = h * (float)(int16_t)(w & 0xffffu), uy = h * (float)(int16_t)(w >> 16);
+            float4 *d = reinterpret_cast<float4 *>(lds + 4 * j);
+            d[0] = make_float4(ux, uy, uy, -ux);    // U_0 = u, U_1 = -j u
+            d[1] = make_float4(-ux, -uy, -uy, ux);  // U_2 = -u, U_3 = j u
         }
-        for (int j = T4; j < T; ++j) mac(j & 3, j);
-        float *dst = a.out + 2 * ((int64_t)t * a.ld + o);
-        dst[0] = (ar[0] + ar[1]) + (ar[2] + ar[3]);
-        dst[1] = (ai[0] + ai[1]) + (ai[2] + ai[3]);
+        __syncthreads();
+        if (live) {
+            auto mac = [&](int q, uint64_t phk, uint32_t jb, int k) {
+                const uint32_t hi = (uint32_t)(phk >> 32);
+                const float2 p = *reinterpret_cast<const float2 *>(pt + ((hi >> 13) & 0x1fff8u));
+                // quadrant copy address as one shift-and-add (the empty asm stops
+                // the shift pair being rewritten as shift + mask + add)
+                uint32_t g = hi >> 30;
+                asm("" : "+v"(g));
+                const uint32_t ua = (g << 3) + jb;
+                const float2 uu = *reinterpret_cast<const float2 *>(ub + ua + 32 * k);
+                // U_g * conj(cos + j sin)
+                ar[q] = __builtin_fmaf(uu.x, p.x, ar[q]);
+                ar[q] = __builtin_fmaf(uu.y, p.y, ar[q]);
+                ai[q] = __builtin_fmaf(uu.y, p.x, ai[q]);
+                ai[q] = __builtin_fmaf(-uu.x, p.y, ai[q]);
+            };
+            const int len8 = len & ~7;
+            for (int j = 0; j < len8; j += 8) {
+                // one phase chain: keep the compiler from splitting it into
+                // eight strided accumulators (seven extra 64-bit adds)
+                asm volatile("" : "+v"(ph));
+                uint64_t p = ph;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    mac(k & 3, p, 32u * (uint32_t)j, k);
+                    p += inc;
+                }
+                ph = p;
+            }
+            for (int j = len8; j < len; ++j) {
+                mac(j & 3, ph, 32u * (uint32_t)j, 0);
+                ph += inc;
+            }
+        }
+    }
+    if (live) {
+        float2 *dst = reinterpret_cast<float2 *>(a.out) + (t * a.ld + o);
+        *dst = make_float2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
     }
 }
 
@@ -98,54 +124,56 @@ __device__ __forceinline__ void ddc_tail(const DdcLaunch &a, int lwg, int G)
 }
 
 template <int WG>
-__device__ __forceinline__ void load_table(const float *src, float *stab)
+__device__ __forceinline__ void load_table(const float *src, float2 *lds)
 {
     const float4 *s4 = reinterpret_cast<const float4 *>(src);
-    float4 *d4 = reinterpret_cast<float4 *>(stab);
+    float4 *d4 = reinterpret_cast<float4 *>(lds + 4 * kUChunk);
     for (int i = threadIdx.x; i < kSinTabLen / 4; i += WG) d4[i] = s4[i];
 }
 
+// Work-group b of G takes units [b W / G, (b+1) W / G) of the W = TC * nout
+// (tone chunk, output) units, outputs fastest.
 template <int WG>
 __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
 {
-    __shared__ float stab[kSinTabLen];
-    __shared__ cf u[4096];
-    load_table<WG>(a.sintab, stab);
+    __shared__ float2 lds[kDdcLds];
+    load_table<WG>(a.sintab, lds);
     const int TC = (a.ntones + WG - 1) / WG;
-    const int64_t nitems = (int64_t)TC * a.nout;
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x)
-        ddc_unit<WG>(a, (int)(it % TC), it / TC, stab, u);
+    const int64_t W = (int64_t)TC * a.nout;
+    const int64_t b = W * blockIdx.x / gridDim.x, e = W * (blockIdx.x + 1) / gridDim.x;
+    for (int64_t it = b; it < e; ++it) ddc_unit<WG>(a, (int)(it / a.nout), it % a.nout, lds);
     ddc_tail<WG>(a, blockIdx.x, gridDim.x);
 }
 
-// Grouped launch over the banks of many streams: work units are (tone chunk,
-// output) pairs of every item plus one tail unit per item; work-groups stride
-// over all of them.  The sine table is the same for every bank and is loaded
-// once per work-group.
+// Grouped launch over the banks of many streams: the units of item i are its
+// (tone chunk, output) pairs, outputs fastest, then one tail unit; work-group
+// b of G takes the contiguous units [b W / G, (b+1) W / G) of the whole list.
+// The table is the same for every bank and is loaded once per work-group.
 __global__ void __launch_bounds__(kDdcGroupWG) ddc_group(const GroupHeader *hdr, const DdcItem *items)
 {
     constexpr int WG = kDdcGroupWG;
-    __shared__ float stab[kSinTabLen];
-    __shared__ cf u[4096];
+    __shared__ float2 lds[kDdcLds];
     const int nitems = hdr->count;
     const int64_t total = hdr->total;
-    if (nitems <= 0 || (int64_t)blockIdx.x >= total) return;
-    load_table<WG>(items[0].a.sintab, stab);
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        int lo = 0, hi = nitems - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].unit_begin <= w) lo = mid;
-            else hi = mid - 1;
-        }
+    if (nitems <= 0) return;
+    const int64_t b = total * blockIdx.x / gridDim.x, e = total * (blockIdx.x + 1) / gridDim.x;
+    if (b >= e) return;
+    load_table<WG>(items[0].a.sintab, lds);
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].unit_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    for (int64_t w = b; w < e; ++w) {
+        while (lo + 1 < nitems && items[lo + 1].unit_begin <= w) ++lo;
         const DdcItem &it = items[lo];
         const int64_t k = w - it.unit_begin;
         const int TC = (it.a.ntones + WG - 1) / WG;
         const int64_t nunits = (int64_t)TC * it.a.nout;
         if (k < nunits) {
-            ddc_unit<WG>(it.a, (int)(k % TC), k / TC, stab, u);
+            ddc_unit<WG>(it.a, (int)(k / it.a.nout), k % it.a.nout, lds);
         } else {
-            __syncthreads();
             ddc_tail<WG>(it.a, 0, 1);
         }
     }

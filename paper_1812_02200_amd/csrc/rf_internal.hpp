@@ -39,7 +39,7 @@ struct DdcLaunch {
     const float *wrev;      // reversed taps: wrev[j] = h[T-1-j]
     const uint64_t *inc;    // [ntones]
     const uint64_t *phi0;   // [ntones]
-    const float *sintab;    // half-wave sine table, 2^15 floats
+    const float *sintab;    // quarter-wave (cos, sin) pair table, 2^14 pairs
     uint64_t base_abs;      // absolute sample index of virtual sample 0
     int64_t nout;           // outputs per tone this call
     uint64_t *phase_out;    // [ntones]: phi0 + phase_at * inc
@@ -101,6 +101,6 @@ hipError_t launch_ddc_group(const GroupHeader *hdr, const DdcItem *items, int gr
 int ddc_default_grid(int ntones, int64_t nout);
 
 // Number of float entries of the half-wave sine table.
-constexpr int kSinTabLen = 1 << 15;
+constexpr int kSinTabLen = 1 << 15;   // floats in the DDC oscillator table (2^14 cos/sin pairs)
 
 }  // namespace rfk

@@ -605,15 +605,16 @@ size_t ddc_footprint(int ntones, int T)
 
 namespace {
 
-// Half-wave sine table: S[i] = sin(2 pi i / 2^16), i in [0, 2^15), built from
-// the quarter wave q[j] = fp32(sin(pi j / 2^15)) so every entry equals the
-// corresponding entry of the full FP32 table up to sign.
+// Quarter-wave (cos, sin) pair table: entry r in [0, 2^14) holds
+// (q[2^14 - r], q[r]) with q[j] = fp32(sin(pi j / 2^15)), i.e. the FP32
+// (cos, sin) of 2 pi r / 2^16; the other three quadrants follow from it by
+// exact sign changes and swaps.
 void fill_sintab(float *tab)
 {
     const double pi = 3.14159265358979323846264338327950288;
-    for (int i = 0; i < rfk::kSinTabLen; ++i) {
-        int j = i <= (1 << 14) ? i : (1 << 15) - i;
-        tab[i] = (float)sin(pi * (double)j / 32768.0);
+    for (int r = 0; r < rfk::kSinTabLen / 2; ++r) {
+        tab[2 * r] = (float)sin(pi * (double)((1 << 14) - r) / 32768.0);
+        tab[2 * r + 1] = (float)sin(pi * (double)r / 32768.0);
     }
 }
 
