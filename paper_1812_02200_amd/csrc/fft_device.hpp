@@ -12,7 +12,7 @@
 
 namespace rfk {
 
-struct cf {
+struct alignas(8) cf {
     float x, y;
 };
 

@@ -262,9 +262,10 @@ __device__ __forceinline__ void fir_phase(const FirState<N, M> &st, cf *lds, int
             v[k] = s;
         }
         dft4(v[0], v[1], v[2], v[3]);
-        const int fb = (g * 4 + qf) * N;
+        // entries 4c .. 4c+3 never straddle a padding point (every 64)
+        cf *dst = lds + lpad((g * 4 + qf) * N + 4 * c);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) lds[lpad(fb + 4 * c + r)] = v[r];
+        for (int r = 0; r < 4; ++r) dst[r] = v[r];
     }
 }
 
