@@ -355,7 +355,7 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
         for (int i = 0; i < W; ++i)
 #pragma unroll
             for (int k = 0; k < 4; ++k) st.xw[i][k].set(base[i * N + k * L]);
-        for (int ph = 0; ph < nph; ++ph) {
+        auto phase = [&](int ph) __attribute__((always_inline)) {
             cf *lds = lds_all + (VV::DBUF ? (ph & 1) * P::LDS : 0);
             uint32_t pre[4][4];
             const bool more = ph + 1 < nph;
@@ -373,7 +373,18 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             if constexpr (SYNC2) group_sync<true>();
             else wave_fence();
             if (more) shift_window<N, M>(st, pre);
+        };
+        // Three phases bring in 12 blocks; for M <= 9 that is more than the
+        // window holds, so in a group of three no window value survives to the
+        // loop edge and the window needs no register rotation there (a move
+        // per value).
+        int ph = 0;
+        for (; ph + 3 <= nph; ph += 3) {
+            phase(ph);
+            phase(ph + 1);
+            phase(ph + 2);
         }
+        for (; ph < nph; ++ph) phase(ph);
     } else {
 #pragma unroll
         for (int i = 0; i < W; ++i) {
