@@ -16,6 +16,9 @@ in the "ddc" object.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +31,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector, published (packed FP32 included)
+# The kernels are built without packed FP32 (two-lane v_pk_* forms), so the
+# FP32 FMA ceiling they can reach is half of that: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flop x 2.4 GHz.  VALU issue: 256 x 4 x 16 x 2.4e9 lane-instructions/s.
+FP32_FMA_PEAK_TF = 78.6
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_pfb_n1024_m8_ddc_1000tones.md")
+KERNEL_SOURCES = os.path.join(ROOT, "paper_1812_02200_amd", "csrc")
 METRIC = "sustained Msamples/s (N=1024 PFB, 1000-tone DDC) + p99 buffer latency"
 
 
@@ -36,12 +46,122 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "pfb", "ddc", "precision", "serving"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "pfb", "ddc", "precision", "serving", "copyprobe"])
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget per oracle baseline sample")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_FETCH_DIR",
+                                                       "PROBE_WRITE_DIR"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script "
+                         "(bench workloads, then --workload copyprobe) as markdown, and exit")
     return ap.parse_args()
+
+
+# ------------------------------------------------------- HBM traffic (PMC)
+
+def sources_digest():
+    """SHA-256 over the kernel sources: counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(KERNEL_SOURCES, "*.hip")) +
+                    glob.glob(os.path.join(KERNEL_SOURCES, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if line.startswith("traffic-json: "):
+                    rec = json.loads(line[len("traffic-json: "):])
+                    if rec.get("sources_sha256") != sources_digest():
+                        return None
+                    k = rec.get("kernels", {}).get(kernel)
+                    return None if k is None else float(k["hbm_bytes_per_launch"])
+    except OSError:
+        return None
+    return None
+
+
+COPY_PROBE_ELEMS = 1 << 26     # int32 elements per probe copy: 256 MiB read, 256 MiB written
+
+
+def bench_copyprobe(torch):
+    """A plain elementwise copy (torch.neg on int32) of known size, to calibrate
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.randint(-1000, 1000, (COPY_PROBE_ELEMS,), dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return {"copyprobe": {"bytes_read": 4 * COPY_PROBE_ELEMS, "bytes_written": 4 * COPY_PROBE_ELEMS,
+                          "launches": 5}}
+
+
+def _pmc_rows(d):
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, match):
+    """{(kernel, grid): [counter value per dispatch]} for kernels whose name contains `match`."""
+    out = {}
+    for r in rows:
+        if match in r["Kernel_Name"]:
+            out.setdefault((r["Kernel_Name"].split("(")[0], int(r["Grid_Size"])), []).append(
+                float(r["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, pf_dir, pw_dir):
+    fr, wr, pfr, pwr = (_pmc_rows(d) for d in (fetch_dir, write_dir, pf_dir, pw_dir))
+    # calibration: the copy probe's five torch.neg dispatches are its last ones
+    def last5(rows):
+        rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+        return [float(r["Counter_Value"]) for r in rows[-5:]]
+    pf, pw = last5(pfr), last5(pwr)
+    want = 4.0 * COPY_PROBE_ELEMS / 1024.0          # KiB read = KiB written per probe launch
+    f_scale = want / np.median(pf)
+    w_scale = want / np.median(pw)
+    lines = ["| kernel | grid (threads) | launches | FETCH_SIZE KiB/launch | WRITE_SIZE KiB/launch |"
+             " HBM bytes/launch (scaled) | algorithmic bytes/launch | ratio |",
+             "|---|---|---|---|---|---|---|---|"]
+    alg = {"pfb_fir_fft": 12.0 * (1 << 24), "ddc_bank": None}
+    kern = {}
+    for name in ("pfb_fir_fft", "ddc_bank"):
+        fd, wd = _per_dispatch(fr, name), _per_dispatch(wr, name)
+        if not fd or not wd:
+            continue
+        # the timed launches are the most frequent shape (the tuner's trials are few each)
+        key = max(fd, key=lambda k: len(fd[k]))
+        fk, wk = float(np.median(fd[key])), float(np.median(wd.get(key, [np.nan])))
+        hbm = fk * 1024 * f_scale + wk * 1024 * w_scale
+        a = alg[name]
+        if name == "ddc_bank":
+            # 2^23 input samples (4 B) + 1000 tones x 8388.6 outputs (8 B) per launch
+            a = 4.0 * (1 << 23) + 8.0 * 1000 * ((1 << 23) / 1000.0)
+        kern[name] = {"grid": key[1], "launches": len(fd[key]), "fetch_kib": fk, "write_kib": wk,
+                      "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": a}
+        lines.append("| %s | %d | %d | %.1f | %.1f | %.4g | %.4g | %.3f |"
+                     % (name, key[1], len(fd[key]), fk, wk, hbm, a, hbm / a))
+    rec = {"sources_sha256": sources_digest(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernels": kern}
+    print("Counter scale factors from the copy probe (torch.neg over %d int32, %.0f KiB read and "
+          "written per launch): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f (medians %.1f / %.1f KiB)."
+          % (COPY_PROBE_ELEMS, want, f_scale, w_scale, np.median(pf), np.median(pw)))
+    print()
+    print("\n".join(lines))
+    print()
+    print("traffic-json: " + json.dumps(rec))
 
 
 def log(*a):
@@ -96,7 +216,9 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
         "kernel_us": kern_s * 1e6,
         "tuned": {"run_len": tuned[1], "variant": tuned[2], "us_per_launch": tuned[0]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("pfb_fir_fft"),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-probe scaled)",
                      "per_launch": "12 B x 2^24 samples = %.1f MB" % (bytes_per_launch / 1e6)},
         "config": {"workload": w.name + ", 2^28 int16 I/Q samples in 2^24-sample buffers",
                    "N": w.N, "M": w.M, "buffer_samples": w.buffer, "samples_per_step": w.nsamples},
@@ -159,6 +281,9 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     kern_s = ms / 1e3 / launches
     flop = 8.0 * w.h.size * w.words.size * outs / launches    # one complex MAC per tap-tone
     achieved = flop / kern_s / 1e12
+    # VALU issue: 9 instructions per sample-tone (64-bit phase step, two table
+    # and copy addresses, four FMAs) against the chip's lane-instruction rate
+    valu = 9.0 * w.h.size * w.words.size * outs / launches / kern_s
     return {
         "value": steps * w.nsamples / (ms / 1e3) / 1e6,
         "unit": "Msamples/s",
@@ -166,8 +291,11 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
         "kernel_us": kern_s * 1e6,
         "outputs_per_tone_per_step": outs / steps,
         "tuned": {"grid": dtuned[1], "us_per_launch": dtuned[0]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TF,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TF, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_FMA_PEAK_TF,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_FMA_PEAK_TF,
+                     "traffic": profiled_traffic("ddc_bank"),
+                     "traffic_unit": "HBM bytes per launch",
+                     "valu_issue_frac": valu / VALU_ISSUE_PEAK,
                      "per_launch": "8 flop x 1024 taps x 1000 tones x %.1f outputs" % (outs / launches)},
         "config": {"workload": w.name + ", 2^27 int16 I/Q samples in 2^23-sample buffers",
                    "ntones": int(w.words.size), "T": int(w.h.size), "D": w.D,
@@ -296,6 +424,9 @@ def cpu_ddc(oracle, w, d, budget_s):
 
 def main():
     a = parse()
+    if a.pmc_summary:
+        pmc_summary(*a.pmc_summary)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported" % a.gpus}))
         sys.exit(2)
@@ -311,6 +442,9 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {}, "device": torch.cuda.get_device_name(0)}
     keep = {}
+    if a.workload == "copyprobe":
+        print(json.dumps(bench_copyprobe(torch)))
+        return
     if a.workload in ("all", "pfb"):
         r, keep["pfb"] = bench_pfb(rf, torch, siggen, a.steps, a.warmup)
         rec["value"] = r["value"]

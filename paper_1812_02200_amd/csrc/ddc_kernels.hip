@@ -36,12 +36,13 @@ __device__ __forceinline__ uint32_t dvload(const VStream &vs, int64_t v)
     return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
 }
 
-// One work unit: output o of tone chunk tc (tones tc*WG .. tc*WG+WG-1).
-// `lds` holds the four rotated input copies (first 4*kUChunk entries) and the
-// pair table (loaded by the caller).  Contains two barriers per tap chunk;
-// every thread of the work-group must call it.
+// One work unit: output o of tone chunk tc (tones tc*WG .. tc*WG+WG-1); the
+// thread's tone's value is returned.  `lds` holds the four rotated input
+// copies (first 4*kUChunk entries) and the pair table (loaded by the caller).
+// Contains two barriers per tap chunk; every thread of the work-group must
+// call it.
 template <int WG>
-__device__ __forceinline__ void ddc_unit(const DdcLaunch &a, int tc, int64_t o, float2 *lds)
+__device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o, float2 *lds)
 {
     const int tid = threadIdx.x;
     const VStream &vs = a.vs;
@@ -105,9 +106,27 @@ __device__ __forceinline__ void ddc_unit(const DdcLaunch &a, int tc, int64_t o, 
             }
         }
     }
-    if (live) {
+    return make_float2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
+}
+
+// Up to kRun consecutive outputs o .. o+cnt-1 of tone chunk tc, kept in
+// registers and stored together: a tone's row segment leaves as back-to-back
+// stores, so its cache lines are complete before they are written back (one
+// 8-byte store per output would reach HBM as partial-line writes).
+constexpr int kRun = 8;
+template <int WG>
+__device__ __forceinline__ void ddc_run(const DdcLaunch &a, int tc, int64_t o, int cnt, float2 *lds)
+{
+    float2 res[kRun];
+#pragma unroll
+    for (int r = 0; r < kRun; ++r)
+        if (r < cnt) res[r] = ddc_unit<WG>(a, tc, o + r, lds);
+    const int t = tc * WG + (int)threadIdx.x;
+    if (t < a.ntones) {
         float2 *dst = reinterpret_cast<float2 *>(a.out) + (t * a.ld + o);
-        *dst = make_float2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
+#pragma unroll
+        for (int r = 0; r < kRun; ++r)
+            if (r < cnt) dst[r] = res[r];
     }
 }
 
@@ -141,7 +160,13 @@ __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
     const int TC = (a.ntones + WG - 1) / WG;
     const int64_t W = (int64_t)TC * a.nout;
     const int64_t b = W * blockIdx.x / gridDim.x, e = W * (blockIdx.x + 1) / gridDim.x;
-    for (int64_t it = b; it < e; ++it) ddc_unit<WG>(a, (int)(it / a.nout), it % a.nout, lds);
+    for (int64_t it = b; it < e;) {
+        const int tc = (int)(it / a.nout);
+        const int64_t o = it - (int64_t)tc * a.nout;
+        const int cnt = (int)min((int64_t)kRun, min(e - it, a.nout - o));
+        ddc_run<WG>(a, tc, o, cnt, lds);
+        it += cnt;
+    }
     ddc_tail<WG>(a, blockIdx.x, gridDim.x);
 }
 
@@ -165,16 +190,21 @@ __global__ void __launch_bounds__(kDdcGroupWG) ddc_group(const GroupHeader *hdr,
         if (items[mid].unit_begin <= b) lo = mid;
         else hi = mid - 1;
     }
-    for (int64_t w = b; w < e; ++w) {
+    for (int64_t w = b; w < e;) {
         while (lo + 1 < nitems && items[lo + 1].unit_begin <= w) ++lo;
         const DdcItem &it = items[lo];
         const int64_t k = w - it.unit_begin;
         const int TC = (it.a.ntones + WG - 1) / WG;
         const int64_t nunits = (int64_t)TC * it.a.nout;
         if (k < nunits) {
-            ddc_unit<WG>(it.a, (int)(k / it.a.nout), k % it.a.nout, lds);
+            const int tc = (int)(k / it.a.nout);
+            const int64_t o = k - (int64_t)tc * it.a.nout;
+            const int cnt = (int)min((int64_t)kRun, min(e - w, it.a.nout - o));
+            ddc_run<WG>(it.a, tc, o, cnt, lds);
+            w += cnt;
         } else {
             ddc_tail<WG>(it.a, 0, 1);
+            ++w;
         }
     }
 }
