@@ -838,9 +838,19 @@ int ddc_destroy(rf_ddc_t p)
 
 namespace {
 
-// Bytes of scratch traffic the tuner spreads its launches over (twice the
-// MI355X's 256 MB last-level cache), so timings reflect HBM, not cache.
-constexpr uint64_t kTuneFootprint = 512ull << 20;
+// Bytes of scratch the tuner spreads its launches over (eight times the
+// MI355X's 256 MB last-level cache, so that a launch's data is no longer
+// cached when it comes round again and timings reflect HBM streaming), capped
+// at a quarter of the free device memory.
+constexpr uint64_t kTuneFootprint = 2048ull << 20;
+
+uint64_t tune_footprint()
+{
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 512ull << 20;
+    const uint64_t q = (uint64_t)fr / 4;
+    return q < kTuneFootprint ? q : kTuneFootprint;
+}
 
 std::string tune_cache_path()
 {
@@ -955,11 +965,11 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     if (rc) return rc;
     const uint64_t F = (nsamples - (uint64_t)p->N * p->M) / p->N + 1;
     // Rotate over enough scratch copies that their traffic exceeds the 256 MB
-    // last-level cache, as a long stream does.
+    // last-level cache several times over, as a long stream does.
     const uint64_t per = nsamples * 4 + F * p->N * 8;
-    int copies = (int)((kTuneFootprint + per - 1) / per);
+    int copies = (int)((tune_footprint() + per - 1) / per);
     if (copies < 1) copies = 1;
-    if (copies > 32) copies = 32;
+    if (copies > 64) copies = 64;
     uint32_t *in = nullptr, *hist = nullptr;
     float *out = nullptr;
     if ((rc = dev_alloc(&in, nsamples * copies, "tune input")) ||
@@ -987,6 +997,9 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     double best = 1e30;
     int best_rl = 0, best_var = 0;
     int k = 0;
+    // two passes over every shape (best of both), so a clock ramp or a
+    // transient does not decide the choice
+    for (int pass = 0; pass < 2 && rc == RF_OK; ++pass)
     for (int rl : rls) {
         for (int var = 0; var < nvar; ++var) {
             a.run_len = rl;
