@@ -64,9 +64,11 @@ def _load():
         lib.orc_nco_phases.argtypes = [P, P, I, U, P]
         lib.orc_ddc_noutputs.argtypes = [I, I, I]
         lib.orc_ddc_noutputs.restype = I
-        lib.orc_ddc.argtypes = [P, P, I, I, P, P, I, P, I, ctypes.c_int, P]
+        lib.orc_chirp_phase.argtypes = [U, U, U, U]
+        lib.orc_chirp_phase.restype = U
+        lib.orc_ddc.argtypes = [P, P, I, I, P, P, P, I, P, I, ctypes.c_int, P]
         lib.orc_ddc.restype = I
-        lib.orc_ddc_points.argtypes = [P, P, I, P, P, I, P, I, P, P, I, ctypes.c_int, P]
+        lib.orc_ddc_points.argtypes = [P, P, I, P, P, P, I, P, I, P, P, I, ctypes.c_int, P]
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -165,6 +167,12 @@ def nco_phase(phi0: int, inc: int, m: int) -> int:
     return int(_load().orc_nco_phase(phi0 & (2**64 - 1), inc & (2**64 - 1), m & (2**64 - 1)))
 
 
+def chirp_phase(phi0: int, inc: int, K: int, m: int) -> int:
+    """phi0 + m*inc + K*m(m-1)/2 mod 2^64 (quadratic NCO of Eq. 1)."""
+    M64 = 2**64 - 1
+    return int(_load().orc_chirp_phase(phi0 & M64, inc & M64, K & M64, m & M64))
+
+
 def nco_phases(inc, phi0, S: int) -> np.ndarray:
     inc = np.ascontiguousarray(inc, dtype=np.uint64)
     p0 = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.uint64)
@@ -177,26 +185,38 @@ def ddc_noutputs(S: int, T: int, D: int) -> int:
     return int(_load().orc_ddc_noutputs(S, T, D))
 
 
-def ddc(inc, phi0, h, D: int, iq=None, x=None, exact_nco: bool = False) -> np.ndarray:
-    """All DDC outputs, complex128 [ntones x nout] (tone-major)."""
+def _chirp_arg(chirp, n):
+    if chirp is None:
+        return None
+    c = np.ascontiguousarray(chirp, dtype=np.uint64)
+    if c.shape != (n,):
+        raise ValueError("chirp must hold one word per tone")
+    return c
+
+
+def ddc(inc, phi0, h, D: int, iq=None, x=None, exact_nco: bool = False, chirp=None) -> np.ndarray:
+    """All DDC outputs, complex128 [ntones x nout] (tone-major).  chirp: K per
+    tone for quadratic-phase (chirped) tones, None for the linear NCO."""
     iqa, xc, S = _stream_args(iq, x)
     inc = np.ascontiguousarray(inc, dtype=np.uint64)
     p0 = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.uint64)
+    ck = _chirp_arg(chirp, inc.size)
     h = np.ascontiguousarray(h, dtype=np.float64)
     T = h.size
     nout = ddc_noutputs(S, T, D)
     out = np.empty((inc.size, nout), dtype=np.complex128)
-    _load().orc_ddc(_ptr(iqa), _ptr(xc), S, inc.size, _ptr(inc), _ptr(p0), T, _ptr(h), D,
-                    int(bool(exact_nco)), _ptr(out.view(np.float64)))
+    _load().orc_ddc(_ptr(iqa), _ptr(xc), S, inc.size, _ptr(inc), _ptr(p0), _ptr(ck), T, _ptr(h),
+                    D, int(bool(exact_nco)), _ptr(out.view(np.float64)))
     return out
 
 
 def ddc_points(inc, phi0, h, D: int, tone_idx, out_idx, iq=None, x=None,
-               exact_nco: bool = False) -> np.ndarray:
+               exact_nco: bool = False, chirp=None) -> np.ndarray:
     """Selected DDC outputs y[tone_idx[i], out_idx[i]], complex128 [npts]."""
     iqa, xc, S = _stream_args(iq, x)
     inc = np.ascontiguousarray(inc, dtype=np.uint64)
     p0 = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.uint64)
+    ck = _chirp_arg(chirp, inc.size)
     h = np.ascontiguousarray(h, dtype=np.float64)
     ti = np.ascontiguousarray(tone_idx, dtype=np.int64)
     oi = np.ascontiguousarray(out_idx, dtype=np.int64)
@@ -205,7 +225,7 @@ def ddc_points(inc, phi0, h, D: int, tone_idx, out_idx, iq=None, x=None,
     if ti.size and (ti.min() < 0 or ti.max() >= inc.size):
         raise ValueError("tone index out of range")
     out = np.empty(ti.size, dtype=np.complex128)
-    _load().orc_ddc_points(_ptr(iqa), _ptr(xc), S, _ptr(inc), _ptr(p0), h.size, _ptr(h), D,
+    _load().orc_ddc_points(_ptr(iqa), _ptr(xc), S, _ptr(inc), _ptr(p0), _ptr(ck), h.size, _ptr(h), D,
                            _ptr(ti), _ptr(oi), ti.size, int(bool(exact_nco)),
                            _ptr(out.view(np.float64)))
     return out

@@ -33,6 +33,14 @@
  * The paper's own anti-alias filter (a moving average) is the special case
  * h = 1/D, T = D.
  *
+ * Chirped tones (paper Sec. III.C, Eq. 1: phase 2 pi (f0 t + k t^2)): the
+ * phase becomes quadratic in the sample index,
+ *     phi_t[m] = phi0_t + m*inc_t + K_t * m(m-1)/2   (mod 2^64),
+ * the closed form of a second-order accumulator (phase += rate; rate += K).
+ * Sampling Eq. 1 at t = m/fs gives exactly this with inc = (f0/fs + k/fs^2)
+ * 2^64 and K = (2k/fs^2) 2^64: Eq. 1 is taken as printed, so the
+ * instantaneous frequency f0 + 2kt ramps at 2k.  K = 0 is the linear NCO.
+ *
  * Parity status: every function here is pinned by the CPU tests in
  * tests/test_oracle_pins.py (closed forms, brute force, library routines,
  * invariants); none is "parity unpinned".
@@ -253,6 +261,19 @@ uint64_t orc_nco_phase(uint64_t phi0, uint64_t inc, uint64_t m)
     return phi0 + m * inc;
 }
 
+/* m(m-1)/2 mod 2^64, exactly: halve whichever factor is even first. */
+static uint64_t orc_tri(uint64_t m)
+{
+    if (m == 0) return 0;
+    return (m % 2 == 0) ? (m / 2) * (m - 1) : m * ((m - 1) / 2);
+}
+
+/* Phase of a chirped NCO at absolute sample m (K = 0: linear). */
+uint64_t orc_chirp_phase(uint64_t phi0, uint64_t inc, uint64_t K, uint64_t m)
+{
+    return phi0 + m * inc + K * orc_tri(m);
+}
+
 /* Phases after S samples, one per tone. */
 void orc_nco_phases(const uint64_t *phi0, const uint64_t *inc, int64_t ntones,
                     uint64_t S, uint64_t *out)
@@ -272,14 +293,14 @@ int64_t orc_ddc_noutputs(int64_t S, int64_t T, int64_t D)
  * (the method); exact_nco = 1: c = exp(i 2 pi phi / 2^64) without
  * truncation (used only to bound the truncation error in tests). */
 static void orc_ddc_one(const int16_t *iq, const double *xc, uint64_t inc,
-                        uint64_t phi0, int64_t T, const double *h, int64_t D,
-                        int64_t n, int exact_nco, const double *tab,
+                        uint64_t phi0, uint64_t K, int64_t T, const double *h,
+                        int64_t D, int64_t n, int exact_nco, const double *tab,
                         double *yr, double *yi)
 {
     double sr = 0.0, si = 0.0;
     for (int64_t k = 0; k < T; ++k) {
         int64_t m = n * D + T - 1 - k;
-        uint64_t phi = orc_nco_phase(phi0, inc, (uint64_t)m);
+        uint64_t phi = orc_chirp_phase(phi0, inc, K, (uint64_t)m);
         double cr, ci;
         if (exact_nco) {
             double a = ORC_TWO_PI * ((double)phi / 18446744073709551616.0);
@@ -303,10 +324,10 @@ static void orc_ddc_one(const int16_t *iq, const double *xc, uint64_t inc,
 }
 
 /* All outputs of all tones: out[(t*nout + n)*2 + {0,1}], tone-major.
- * phi0 may be NULL (all zero).  Returns nout. */
+ * phi0 and chirp (K per tone) may be NULL (all zero).  Returns nout. */
 int64_t orc_ddc(const int16_t *iq, const double *xc, int64_t S, int64_t ntones,
-                const uint64_t *inc, const uint64_t *phi0, int64_t T,
-                const double *h, int64_t D, int exact_nco, double *out)
+                const uint64_t *inc, const uint64_t *phi0, const uint64_t *chirp,
+                int64_t T, const double *h, int64_t D, int exact_nco, double *out)
 {
     int64_t nout = orc_ddc_noutputs(S, T, D);
     double *tab = (double *)malloc(sizeof(double) * 2 * 65536);
@@ -315,8 +336,8 @@ int64_t orc_ddc(const int16_t *iq, const double *xc, int64_t S, int64_t ntones,
     for (int64_t t = 0; t < ntones; ++t)
         for (int64_t n = 0; n < nout; ++n) {
             double *y = out + 2 * (t * nout + n);
-            orc_ddc_one(iq, xc, inc[t], phi0 ? phi0[t] : 0, T, h, D, n,
-                        exact_nco, tab, &y[0], &y[1]);
+            orc_ddc_one(iq, xc, inc[t], phi0 ? phi0[t] : 0, chirp ? chirp[t] : 0,
+                        T, h, D, n, exact_nco, tab, &y[0], &y[1]);
         }
     free(tab);
     return nout;
@@ -325,7 +346,8 @@ int64_t orc_ddc(const int16_t *iq, const double *xc, int64_t S, int64_t ntones,
 /* Selected outputs (tone_idx[i], out_idx[i]) for sampled checks of large
  * runs; points outside the valid range are written as NaN. */
 void orc_ddc_points(const int16_t *iq, const double *xc, int64_t S,
-                    const uint64_t *inc, const uint64_t *phi0, int64_t T,
+                    const uint64_t *inc, const uint64_t *phi0,
+                    const uint64_t *chirp, int64_t T,
                     const double *h, int64_t D, const int64_t *tone_idx,
                     const int64_t *out_idx, int64_t npts, int exact_nco,
                     double *out)
@@ -341,8 +363,8 @@ void orc_ddc_points(const int16_t *iq, const double *xc, int64_t S,
             out[2 * i + 1] = NAN;
             continue;
         }
-        orc_ddc_one(iq, xc, inc[t], phi0 ? phi0[t] : 0, T, h, D, n, exact_nco,
-                    tab, &out[2 * i], &out[2 * i + 1]);
+        orc_ddc_one(iq, xc, inc[t], phi0 ? phi0[t] : 0, chirp ? chirp[t] : 0,
+                    T, h, D, n, exact_nco, tab, &out[2 * i], &out[2 * i + 1]);
     }
     free(tab);
 }

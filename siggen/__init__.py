@@ -93,6 +93,19 @@ def bin_word(k: float, N: int) -> int:
     return int(round(k * TWO64 / N)) % (1 << 64)
 
 
+def chirp_words(f0_hz: float, k_hz_per_s: float, fs: float = FS):
+    """(inc, K) of the quadratic NCO for Eq. 1's phase 2 pi (f0 t + k t^2)
+    sampled at t = m/fs: in cycles, f0 m/fs + k m^2/fs^2 = m (f0/fs + k/fs^2)
+    + (2k/fs^2) m(m-1)/2, so inc = (f0/fs + k/fs^2) 2^64 and K = (2k/fs^2)
+    2^64, each rounded to the nearest integer mod 2^64 (exact rational
+    arithmetic on the given floats)."""
+    from fractions import Fraction
+    f0, k, fs_ = Fraction(f0_hz), Fraction(k_hz_per_s), Fraction(fs)
+    inc = round((f0 / fs_ + k / fs_ ** 2) * (1 << 64)) % (1 << 64)
+    K = round(2 * k / fs_ ** 2 * (1 << 64)) % (1 << 64)
+    return int(inc), int(K)
+
+
 def word_freq(w: int, fs: float = FS) -> float:
     """Frequency in Hz of tuning word w, in [-fs/2, fs/2)."""
     w = int(w) % (1 << 64)

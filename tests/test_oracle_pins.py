@@ -279,6 +279,94 @@ def test_p10_off_grid_tone_within_truncation_bound():
         assert np.allclose(ye, A * np.exp(1j * theta), rtol=0, atol=1e-9 * A)
 
 
+# ------------------------------------- P15-P17: chirped NCO (Sec. III.C, Eq. 1)
+
+def _eq1_cycles_exact(f0, k, fs, m):
+    """Eq. 1's phase in cycles, f0 t + k t^2 at t = m/fs, as an exact rational."""
+    from fractions import Fraction
+    t = Fraction(m) / Fraction(fs)
+    return Fraction(f0) * t + Fraction(k) * t * t
+
+
+def test_p15_chirp_phase_is_eq1_exactly_for_dyadic_parameters():
+    # f0/fs and k/fs^2 dyadic: the words are exact and the integer phase must
+    # equal 2^64 (f0 t + k t^2) mod 2^64 at every sample, however large m is.
+    # A ramp read as k (not 2k) or an m^2 term in place of m(m-1)/2 fails.
+    fs = 2.0**28
+    for f0, k in [(3 * 2.0**20, 5 * 2.0**30), (-(2.0**25), 2.0**33), (0.0, -(7 * 2.0**29))]:
+        inc, K = siggen.chirp_words(f0, k, fs)
+        for m in [0, 1, 2, 3, 1000, 123457, 2**33 + 5, 2**40 + 17]:
+            want = _eq1_cycles_exact(f0, k, fs, m) * 2**64
+            assert want.denominator == 1
+            assert oracle.chirp_phase(0, inc, K, m) == int(want) % 2**64
+
+
+def test_p15_chirp_phase_rounding_bound_for_arbitrary_parameters():
+    # Rounded words: |phase - 2^64 Eq.1| <= m/2 + m(m-1)/4 + 1 (the two word
+    # roundings, each at most 1/2, times m and m(m-1)/2).
+    rng = np.random.default_rng(15)
+    for _ in range(20):
+        f0 = float(rng.uniform(-90e6, 90e6))
+        k = float(rng.uniform(-5e12, 5e12))
+        inc, K = siggen.chirp_words(f0, k)
+        for m in [1, 17, 4096, 10**6, 3 * 10**7]:
+            want = _eq1_cycles_exact(f0, k, siggen.FS, m) * 2**64
+            d = (oracle.chirp_phase(0, inc, K, m) - round(want)) % 2**64
+            d = d - 2**64 if d >= 2**63 else d
+            assert abs(d) <= m / 2 + m * (m - 1) / 4 + 1
+
+
+def test_p16_chirp_closed_form_equals_second_order_accumulator():
+    rng = np.random.default_rng(16)
+    for _ in range(5):
+        p0, inc, K = (int(v) for v in rng.integers(0, 2**64, size=3, dtype=np.uint64))
+        phi, rate = p0, inc
+        for m in range(3000):
+            assert oracle.chirp_phase(p0, inc, K, m) == phi
+            phi = (phi + rate) % 2**64
+            rate = (rate + K) % 2**64
+        assert oracle.chirp_phase(p0, inc, 0, 987654321) == oracle.nco_phase(p0, inc, 987654321)
+
+
+def test_p17_ddc_of_matching_chirp_is_constant_dc():
+    # Input: an unquantised chirp A exp(i (2 pi phi[m]/2^64 + theta)); the DDC
+    # tone follows the same chirp, so every output is A exp(i theta) sum(h),
+    # exactly with the untruncated NCO and within the 16-bit phase truncation
+    # bound with the table.
+    T, D = 96, 40
+    h = siggen.ddc_lowpass(T, 1e6)
+    A, theta = 900.0, 0.7
+    for f0, k in [(12.5e6, 3e12), (-40e6, -8e12), (77e6, 2.5e13)]:
+        inc, K = siggen.chirp_words(f0, k)
+        m0 = 5_000_000                       # start late in the chirp: large quadratic term
+        S = T + 7 * D
+        ph = np.array([oracle.chirp_phase(0, inc, K, m0 + m) for m in range(S)], dtype=np.uint64)
+        x = A * np.exp(1j * (ph.astype(np.float64) * (2 * np.pi / 2.0**64) + theta))
+        # the stream starts at m0: the tone's phase at local sample 0 is phi(m0)
+        # and its rate is inc + K m0
+        p0 = np.array([oracle.chirp_phase(0, inc, K, m0)], dtype=np.uint64)
+        inc0 = np.array([(inc + K * m0) % 2**64], dtype=np.uint64)
+        y = oracle.ddc(inc0, p0, h, D, x=x, chirp=np.array([K], dtype=np.uint64))
+        assert y.shape == (1, 8)
+        assert np.all(np.abs(y - A * np.exp(1j * theta) * h.sum()) <= A * np.abs(h).sum() * 2 * np.pi / 65536)
+        ye = oracle.ddc(inc0, p0, h, D, x=x, chirp=np.array([K], dtype=np.uint64), exact_nco=True)
+        assert np.allclose(ye, A * np.exp(1j * theta) * h.sum(), rtol=0, atol=1e-9 * A)
+        # with the linear NCO (K dropped) the chirp walks out of the passband
+        yl = oracle.ddc(inc0, p0, h, D, x=x)
+        assert np.abs(yl).min() < 0.1 * A
+
+
+def test_p17_zero_chirp_is_the_linear_nco():
+    rng = np.random.default_rng(17)
+    w = siggen.random_words(rng, 5)
+    p0 = siggen.random_words(rng, 5)
+    h = siggen.ddc_lowpass(64, 2e6)
+    iq = siggen.quantize(rng.normal(0, 900, size=3000) + 1j * rng.normal(0, 900, size=3000))
+    a = oracle.ddc(w, p0, h, 25, iq=iq)
+    b = oracle.ddc(w, p0, h, 25, iq=iq, chirp=np.zeros(5, dtype=np.uint64))
+    assert np.array_equal(a, b)
+
+
 # ----------------------------------------------- P11, P12: NCO phase and table
 
 def test_p11_nco_phase_closed_form_bit_exact():
