@@ -284,11 +284,38 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     # VALU issue: 9 instructions per sample-tone (64-bit phase step, two table
     # and copy addresses, four FMAs) against the chip's lane-instruction rate
     valu = 9.0 * w.h.size * w.words.size * outs / launches / kern_s
+    # the same bank with chirped tones (Eq. 1 words; second-order accumulator)
+    crng = np.random.default_rng(33)
+    cinc, cK = [], []
+    for _ in range(w.words.size):
+        a_, b_ = siggen.chirp_words(float(crng.uniform(-90e6, 90e6)), float(crng.uniform(-2e13, 2e13)))
+        cinc.append(a_)
+        cK.append(b_)
+    dc = rf.Ddc(np.array(cinc, np.uint64), w.h, w.D, w.phase0, max_samples_per_call=w.buffer,
+                chirp=np.array(cK, np.uint64))
+    dc.tune(w.buffer)
+
+    def cstep():
+        for b in range(nbuf):
+            dc.process_ptr(base_in + 4 * b * w.buffer, w.buffer, base_out + 8 * b * w.words.size * ld, ld, sh)
+
+    cstep()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        cstep()
+    e1.record(s)
+    torch.cuda.synchronize()
+    cms = e0.elapsed_time(e1)
+    dc.close()
     return {
         "value": steps * w.nsamples / (ms / 1e3) / 1e6,
         "unit": "Msamples/s",
         "ms_per_step": ms / steps,
         "kernel_us": kern_s * 1e6,
+        "chirped": {"value": steps * w.nsamples / (cms / 1e3) / 1e6, "unit": "Msamples/s",
+                    "kernel_us": cms * 1e3 / launches,
+                    "workload": "the same bank with 1000 chirped tones (Eq. 1, |k| <= 2e13 Hz/s)"},
         "outputs_per_tone_per_step": outs / steps,
         "tuned": {"grid": dtuned[1], "us_per_launch": dtuned[0]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_FMA_PEAK_TF,

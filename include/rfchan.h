@@ -152,6 +152,25 @@ int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc,
                const uint64_t *phase0, int32_t ntaps, const float *lpf, int32_t decim,
                uint64_t max_samples_per_call);
 
+/* Create a bank of chirped tones (paper Sec. III.C, Eq. 1: a tone whose phase
+ * is quadratic in time, 2 pi (f0 t + k t^2)).  Tone t's phase at absolute
+ * sample m is
+ *     phi_t[m] = phase0[t] + m * phase_inc[t] + chirp[t] * m(m-1)/2  (mod 2^64),
+ * i.e. a second-order accumulator: the phase advances by a rate that itself
+ * advances by chirp[t] each sample.  Eq. 1 sampled at t = m/fs is exactly this
+ * with phase_inc = (f0/fs + k/fs^2) 2^64 and chirp = (2k/fs^2) 2^64, each
+ * rounded mod 2^64 (Eq. 1 taken as printed: the instantaneous frequency
+ * f0 + 2kt ramps at 2k).  chirp[t] = 0 is an ordinary tone.  Everything else
+ * -- table, mix, low-pass, decimation, ddc_process, state, phase read-back
+ * (ddc_get_phase returns phi_t at the next sample) -- is as for ddc_create.
+ *   chirp      host array [ntones] of 64-bit second-difference words (copied);
+ *              NULL makes this call identical to ddc_create.
+ * Other arguments and errors as ddc_create.  Chirped banks are not accepted
+ * by the serving API (rfs_*), whose stream descriptor has no chirp words. */
+int ddc_create_chirp(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc,
+                     const uint64_t *phase0, const uint64_t *chirp, int32_t ntaps,
+                     const float *lpf, int32_t decim, uint64_t max_samples_per_call);
+
 /* Outputs per tone that the next ddc_process of `nsamples` samples emits. */
 uint64_t ddc_outputs_for(rf_ddc_t ddc, uint64_t nsamples);
 

@@ -77,6 +77,7 @@ SIGNATURES = {
     "pfb_reset": (ctypes.c_int, [_P]),
     "pfb_destroy": (ctypes.c_int, [_P]),
     "ddc_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32, _P, _I32, _U64]),
+    "ddc_create_chirp": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _P, _I32, _P, _I32, _U64]),
     "ddc_outputs_for": (_U64, [_P, _U64]),
     "ddc_process": (ctypes.c_int, [_P, _P, _U64, _P, _U64, ctypes.POINTER(_U64), _P]),
     "ddc_get_phase": (ctypes.c_int, [_P, _P]),
@@ -261,19 +262,30 @@ class Ddc:
     """Direct-demodulation bank handle (ddc_* calls)."""
 
     def __init__(self, phase_inc, lpf, decim: int, phase0=None,
-                 max_samples_per_call: int = 1 << 24):
+                 max_samples_per_call: int = 1 << 24, chirp=None):
+        """chirp: per-tone phase second differences (ddc_create_chirp) for
+        chirped tones, or None for ordinary tones (ddc_create)."""
         import numpy as np
         inc = np.ascontiguousarray(np.asarray(phase_inc, dtype=np.uint64).reshape(-1))
         p0 = None if phase0 is None else np.ascontiguousarray(
             np.asarray(phase0, dtype=np.uint64).reshape(-1))
         if p0 is not None and p0.size != inc.size:
             raise ValueError("phase0 must have one entry per tone")
+        ck = None if chirp is None else np.ascontiguousarray(
+            np.asarray(chirp, dtype=np.uint64).reshape(-1))
+        if ck is not None and ck.size != inc.size:
+            raise ValueError("chirp must have one entry per tone")
         h = np.ascontiguousarray(np.asarray(lpf, dtype=np.float32).reshape(-1))
         self.ntones, self.T, self.D = int(inc.size), int(h.size), int(decim)
         self._h = _P()
-        check(lib().ddc_create(ctypes.byref(self._h), self.ntones, inc.ctypes.data,
-                               None if p0 is None else p0.ctypes.data, self.T, h.ctypes.data,
-                               self.D, int(max_samples_per_call)), "ddc_create")
+        p0p = None if p0 is None else p0.ctypes.data
+        if ck is None:
+            check(lib().ddc_create(ctypes.byref(self._h), self.ntones, inc.ctypes.data, p0p, self.T,
+                                   h.ctypes.data, self.D, int(max_samples_per_call)), "ddc_create")
+        else:
+            check(lib().ddc_create_chirp(ctypes.byref(self._h), self.ntones, inc.ctypes.data, p0p,
+                                         ck.ctypes.data, self.T, h.ctypes.data, self.D,
+                                         int(max_samples_per_call)), "ddc_create_chirp")
         self.max_samples = int(max_samples_per_call)
 
     def outputs_for(self, nsamples: int) -> int:

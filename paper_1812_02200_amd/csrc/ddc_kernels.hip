@@ -19,6 +19,11 @@
 // 128 KiB table in LDS, one read of the quadrant's copy, and four FMAs.  The
 // products are the same FP32 products as with the full 2^16-entry table.
 //
+// Chirped tones (Sec. III.C, Eq. 1) make the phase quadratic in the sample
+// index, phi[m] = phi0 + m inc + K m(m-1)/2 (mod 2^64): the oscillator becomes
+// a second-order accumulator (phase += rate, rate += K), started for each
+// output window from the closed form.  Everything else is unchanged.
+//
 // Each work-group owns a contiguous range of outputs of one tone chunk, so a
 // tone's consecutive outputs are written by one work-group (whole cache
 // sectors reach HBM, not 8-byte fragments from different L2 slices).
@@ -36,12 +41,18 @@ __device__ __forceinline__ uint32_t dvload(const VStream &vs, int64_t v)
     return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
 }
 
+// m(m-1)/2 mod 2^64, exactly (the even factor is halved first).
+__device__ __forceinline__ uint64_t tri64(uint64_t m)
+{
+    return (m & 1) ? m * ((m - 1) >> 1) : (m >> 1) * (m - 1);
+}
+
 // One work unit: output o of tone chunk tc (tones tc*WG .. tc*WG+WG-1); the
 // thread's tone's value is returned.  `lds` holds the four rotated input
 // copies (first 4*kUChunk entries) and the pair table (loaded by the caller).
 // Contains two barriers per tap chunk; every thread of the work-group must
 // call it.
-template <int WG>
+template <int WG, bool CHIRP>
 __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o, float2 *lds)
 {
     const int tid = threadIdx.x;
@@ -50,10 +61,16 @@ __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o
     const int64_t v0 = o * a.D;
     const int t = tc * WG + tid;
     const bool live = t < a.ntones;
-    uint64_t inc = 0, ph = 0;
+    uint64_t inc = 0, ph = 0, K = 0;
     if (live) {
         inc = a.inc[t];
-        ph = a.phi0[t] + (a.base_abs + (uint64_t)v0) * inc;
+        const uint64_t m0 = a.base_abs + (uint64_t)v0;
+        ph = a.phi0[t] + m0 * inc;
+        if constexpr (CHIRP) {
+            K = a.chirp[t];
+            ph += K * tri64(m0);
+            inc += K * m0;      // the phase step from sample m0 to m0+1
+        }
     }
     // four interleaved partial sums (j mod 4): independent FMA chains
     float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
@@ -91,18 +108,20 @@ __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o
             for (int j = 0; j < len8; j += 8) {
                 // one phase chain: keep the compiler from splitting it into
                 // eight strided accumulators (seven extra 64-bit adds)
-                asm volatile("" : "+v"(ph));
+                asm volatile("" : "+v"(ph), "+v"(inc));
                 uint64_t p = ph;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     mac(k & 3, p, 32u * (uint32_t)j, k);
                     p += inc;
+                    if constexpr (CHIRP) inc += K;
                 }
                 ph = p;
             }
             for (int j = len8; j < len; ++j) {
                 mac(j & 3, ph, 32u * (uint32_t)j, 0);
                 ph += inc;
+                if constexpr (CHIRP) inc += K;
             }
         }
     }
@@ -114,13 +133,13 @@ __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o
 // stores, so its cache lines are complete before they are written back (one
 // 8-byte store per output would reach HBM as partial-line writes).
 constexpr int kRun = 8;
-template <int WG>
+template <int WG, bool CHIRP>
 __device__ __forceinline__ void ddc_run(const DdcLaunch &a, int tc, int64_t o, int cnt, float2 *lds)
 {
     float2 res[kRun];
 #pragma unroll
     for (int r = 0; r < kRun; ++r)
-        if (r < cnt) res[r] = ddc_unit<WG>(a, tc, o + r, lds);
+        if (r < cnt) res[r] = ddc_unit<WG, CHIRP>(a, tc, o + r, lds);
     const int t = tc * WG + (int)threadIdx.x;
     if (t < a.ntones) {
         float2 *dst = reinterpret_cast<float2 *>(a.out) + (t * a.ld + o);
@@ -137,7 +156,8 @@ __device__ __forceinline__ void ddc_tail(const DdcLaunch &a, int lwg, int G)
 {
     const int tid = threadIdx.x;
     if (lwg == 0)
-        for (int t = tid; t < a.ntones; t += WG) a.phase_out[t] = a.phi0[t] + a.phase_at * a.inc[t];
+        for (int t = tid; t < a.ntones; t += WG)
+            a.phase_out[t] = a.phi0[t] + a.phase_at * a.inc[t] + (a.chirp ? a.chirp[t] * tri64(a.phase_at) : 0);
     for (int64_t i = (int64_t)lwg * WG + tid; i < a.keep_len; i += (int64_t)G * WG)
         a.hist_out[i] = dvload(a.vs, a.keep_from + i);
 }
@@ -152,7 +172,7 @@ __device__ __forceinline__ void load_table(const float *src, float2 *lds)
 
 // Work-group b of G takes units [b W / G, (b+1) W / G) of the W = TC * nout
 // (tone chunk, output) units, outputs fastest.
-template <int WG>
+template <int WG, bool CHIRP>
 __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
 {
     __shared__ float2 lds[kDdcLds];
@@ -164,7 +184,7 @@ __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
         const int tc = (int)(it / a.nout);
         const int64_t o = it - (int64_t)tc * a.nout;
         const int cnt = (int)min((int64_t)kRun, min(e - it, a.nout - o));
-        ddc_run<WG>(a, tc, o, cnt, lds);
+        ddc_run<WG, CHIRP>(a, tc, o, cnt, lds);
         it += cnt;
     }
     ddc_tail<WG>(a, blockIdx.x, gridDim.x);
@@ -174,6 +194,7 @@ __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
 // (tone chunk, output) pairs, outputs fastest, then one tail unit; work-group
 // b of G takes the contiguous units [b W / G, (b+1) W / G) of the whole list.
 // The table is the same for every bank and is loaded once per work-group.
+// Grouped banks have linear oscillators (the serving path has no chirps).
 __global__ void __launch_bounds__(kDdcGroupWG) ddc_group(const GroupHeader *hdr, const DdcItem *items)
 {
     constexpr int WG = kDdcGroupWG;
@@ -200,7 +221,7 @@ __global__ void __launch_bounds__(kDdcGroupWG) ddc_group(const GroupHeader *hdr,
             const int tc = (int)(k / it.a.nout);
             const int64_t o = k - (int64_t)tc * it.a.nout;
             const int cnt = (int)min((int64_t)kRun, min(e - w, it.a.nout - o));
-            ddc_run<WG>(it.a, tc, o, cnt, lds);
+            ddc_run<WG, false>(it.a, tc, o, cnt, lds);
             w += cnt;
         } else {
             ddc_tail<WG>(it.a, 0, 1);
@@ -233,7 +254,10 @@ template <int WG>
 static hipError_t launch_wg(const DdcLaunch &a, hipStream_t s)
 {
     int grid = a.grid > 0 ? a.grid : 256;
-    hipLaunchKernelGGL((ddc_bank<WG>), dim3(grid), dim3(WG), 0, s, a);
+    if (a.chirp)
+        hipLaunchKernelGGL((ddc_bank<WG, true>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((ddc_bank<WG, false>), dim3(grid), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 

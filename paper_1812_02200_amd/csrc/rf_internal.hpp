@@ -39,6 +39,7 @@ struct DdcLaunch {
     const float *wrev;      // reversed taps: wrev[j] = h[T-1-j]
     const uint64_t *inc;    // [ntones]
     const uint64_t *phi0;   // [ntones]
+    const uint64_t *chirp;  // [ntones] phase second differences (chirped tones), or null
     const float *sintab;    // quarter-wave (cos, sin) pair table, 2^14 pairs
     uint64_t base_abs;      // absolute sample index of virtual sample 0
     int64_t nout;           // outputs per tone this call

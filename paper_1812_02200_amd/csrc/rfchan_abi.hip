@@ -444,6 +444,7 @@ struct rf_ddc {
     int device = 0;
     int cus = 256;
     uint64_t *d_inc = nullptr, *d_phi0 = nullptr, *d_phase = nullptr;
+    uint64_t *d_chirp = nullptr;   // phase second differences (chirped tones) or null
     float *d_wrev = nullptr, *d_tab = nullptr;
     uint32_t *d_hist[2] = {nullptr, nullptr};
     int cur = 0;
@@ -451,7 +452,7 @@ struct rf_ddc {
     uint64_t nnext = 0;   // outputs emitted (absolute index of the next output)
     int64_t H = 0;        // retained samples, absolute [S-H, S) == [nnext*D, S)
     uint64_t skip = 0;    // samples of future input before nnext*D (only when D > T)
-    uint64_t *h_inc = nullptr, *h_phi0 = nullptr;
+    uint64_t *h_inc = nullptr, *h_phi0 = nullptr, *h_chirp = nullptr;
     float *h_taps = nullptr;
     int grid = 0;
     StreamOrder order;
@@ -475,6 +476,7 @@ void ddc_free(rf_ddc *p)
     (void)hipFree(p->d_inc);
     (void)hipFree(p->d_phi0);
     (void)hipFree(p->d_phase);
+    (void)hipFree(p->d_chirp);
     (void)hipFree(p->d_wrev);
     (void)hipFree(p->d_tab);
     (void)hipFree(p->d_hist[0]);
@@ -482,6 +484,7 @@ void ddc_free(rf_ddc *p)
     if (p->order.ev) (void)hipEventDestroy(p->order.ev);
     free(p->h_inc);
     free(p->h_phi0);
+    free(p->h_chirp);
     free(p->h_taps);
     delete p;
 }
@@ -503,7 +506,19 @@ uint64_t ddc_fingerprint(const rf_ddc *p)
     mix(p->h_inc, sizeof(uint64_t) * p->ntones);
     mix(p->h_phi0, sizeof(uint64_t) * p->ntones);
     mix(p->h_taps, sizeof(float) * p->T);
+    if (p->h_chirp) mix(p->h_chirp, sizeof(uint64_t) * p->ntones);
     return h;
+}
+
+// m(m-1)/2 mod 2^64, exactly.
+uint64_t tri64(uint64_t m) { return (m & 1) ? m * ((m - 1) >> 1) : (m >> 1) * (m - 1); }
+
+// Phase of tone t at absolute sample m: phi0 + m inc (+ K m(m-1)/2 if chirped).
+uint64_t ddc_phase_at(const rf_ddc *p, int t, uint64_t m)
+{
+    uint64_t ph = p->h_phi0[t] + m * p->h_inc[t];
+    if (p->h_chirp) ph += p->h_chirp[t] * tri64(m);
+    return ph;
 }
 
 struct DdcPlan {
@@ -564,6 +579,7 @@ int ddc_prepare(rf_ddc *p, const int16_t *iq_dev, uint64_t nsamples, float *out_
     a->wrev = p->d_wrev;
     a->inc = p->d_inc;
     a->phi0 = p->d_phi0;
+    a->chirp = p->d_chirp;
     a->sintab = p->d_tab;
     a->base_abs = p->nnext * (uint64_t)p->D;
     a->nout = (int64_t)pl.nout;
@@ -625,6 +641,13 @@ extern "C" {
 int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const uint64_t *phase0, int32_t ntaps,
                const float *lpf, int32_t decim, uint64_t max_samples_per_call)
 {
+    return ddc_create_chirp(out, ntones, phase_inc, phase0, nullptr, ntaps, lpf, decim, max_samples_per_call);
+}
+
+int ddc_create_chirp(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const uint64_t *phase0,
+                     const uint64_t *chirp, int32_t ntaps, const float *lpf, int32_t decim,
+                     uint64_t max_samples_per_call)
+{
     if (!out) return fail(RF_EINVAL, "ddc_create: out is NULL");
     *out = nullptr;
     if (ntones < 1 || ntones > 65536) return fail(RF_EINVAL, "ddc_create: ntones=%d must be in [1, 65536]", ntones);
@@ -654,7 +677,8 @@ int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const u
     p->h_taps = (float *)malloc(sizeof(float) * ntaps);
     float *wrev = (float *)malloc(sizeof(float) * ntaps);
     float *tab = (float *)malloc(sizeof(float) * rfk::kSinTabLen);
-    if (!p->h_inc || !p->h_phi0 || !p->h_taps || !wrev || !tab) {
+    if (chirp) p->h_chirp = (uint64_t *)malloc(sizeof(uint64_t) * ntones);
+    if (!p->h_inc || !p->h_phi0 || !p->h_taps || !wrev || !tab || (chirp && !p->h_chirp)) {
         free(wrev);
         free(tab);
         ddc_free(p);
@@ -662,6 +686,7 @@ int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const u
     }
     memcpy(p->h_inc, phase_inc, sizeof(uint64_t) * ntones);
     if (phase0) memcpy(p->h_phi0, phase0, sizeof(uint64_t) * ntones);
+    if (chirp) memcpy(p->h_chirp, chirp, sizeof(uint64_t) * ntones);
     memcpy(p->h_taps, lpf, sizeof(float) * ntaps);
     for (int j = 0; j < ntaps; ++j) wrev[j] = lpf[ntaps - 1 - j];
     fill_sintab(tab);
@@ -671,7 +696,8 @@ int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const u
         (rc = dev_alloc(&p->d_phase, ntones, "phase")) || (rc = dev_alloc(&p->d_wrev, ntaps, "taps")) ||
         (rc = dev_alloc(&p->d_tab, rfk::kSinTabLen, "table")) ||
         (rc = dev_alloc(&p->d_hist[0], hist_len, "history")) ||
-        (rc = dev_alloc(&p->d_hist[1], hist_len, "history"))) {
+        (rc = dev_alloc(&p->d_hist[1], hist_len, "history")) ||
+        (chirp && (rc = dev_alloc(&p->d_chirp, ntones, "chirp")))) {
         free(wrev);
         free(tab);
         ddc_free(p);
@@ -680,6 +706,8 @@ int ddc_create(rf_ddc_t *out, int32_t ntones, const uint64_t *phase_inc, const u
     e = hipMemcpy(p->d_inc, p->h_inc, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_phi0, p->h_phi0, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_phase, p->h_phi0, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
+    if (e == hipSuccess && chirp)
+        e = hipMemcpy(p->d_chirp, p->h_chirp, sizeof(uint64_t) * ntones, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_wrev, wrev, sizeof(float) * ntaps, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab, sizeof(float) * rfk::kSinTabLen, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);
@@ -787,7 +815,7 @@ int ddc_set_state(rf_ddc_t p, const void *blob, size_t size)
     // phase of the next sample follows from the sample count
     uint64_t *ph = (uint64_t *)malloc(sizeof(uint64_t) * p->ntones);
     if (!ph) return fail(RF_ENOMEM, "ddc_set_state: host allocation");
-    for (int t = 0; t < p->ntones; ++t) ph[t] = p->h_phi0[t] + h.S * p->h_inc[t];
+    for (int t = 0; t < p->ntones; ++t) ph[t] = ddc_phase_at(p, t, h.S);
     hipError_t e = hipMemcpy(p->d_phase, ph, sizeof(uint64_t) * p->ntones, hipMemcpyHostToDevice);
     free(ph);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase)");
@@ -1079,6 +1107,7 @@ int ddc_tune(rf_ddc_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     a.wrev = p->d_wrev;
     a.inc = p->d_inc;
     a.phi0 = p->d_phi0;
+    a.chirp = p->d_chirp;
     a.sintab = p->d_tab;
     a.base_abs = 0;
     a.nout = (int64_t)nout;
