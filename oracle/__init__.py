@@ -64,6 +64,9 @@ def _load():
         lib.orc_nco_phases.argtypes = [P, P, I, U, P]
         lib.orc_ddc_noutputs.argtypes = [I, I, I]
         lib.orc_ddc_noutputs.restype = I
+        lib.orc_tab32.argtypes = [P]
+        lib.orc_tx.argtypes = [I, P, P, P, P, I, P]
+        lib.orc_tx_advance.argtypes = [I, P, P, P, U]
         lib.orc_chirp_phase.argtypes = [U, U, U, U]
         lib.orc_chirp_phase.restype = U
         lib.orc_ddc.argtypes = [P, P, I, I, P, P, P, I, P, I, ctypes.c_int, P]
@@ -229,3 +232,35 @@ def ddc_points(inc, phi0, h, D: int, tone_idx, out_idx, iq=None, x=None,
                            _ptr(ti), _ptr(oi), ti.size, int(bool(exact_nco)),
                            _ptr(out.view(np.float64)))
     return out
+
+
+# ------------------------------------------------------------------ Tx
+
+def tab32() -> np.ndarray:
+    """The FP32 cos/sin table [2^16, 2] by its quarter-wave definition."""
+    tab = np.empty((65536, 2), dtype=np.float32)
+    _load().orc_tab32(_ptr(tab))
+    return tab
+
+
+def tx(phase, rate, amp, n: int, chirp=None) -> np.ndarray:
+    """n samples of the multi-tone transmit buffer, int16 interleaved I/Q [2n],
+    from the oscillator state (phase, rate, chirp) at its first sample."""
+    ph = np.ascontiguousarray(phase, dtype=np.uint64)
+    rt = np.ascontiguousarray(rate, dtype=np.uint64)
+    a = np.ascontiguousarray(amp, dtype=np.float32)
+    if rt.shape != ph.shape or a.shape != ph.shape:
+        raise ValueError("phase, rate and amp need one entry per tone")
+    ck = _chirp_arg(chirp, ph.size)
+    out = np.empty(2 * n, dtype=np.int16)
+    _load().orc_tx(ph.size, _ptr(ph), _ptr(rt), _ptr(ck), _ptr(a), n, _ptr(out))
+    return out
+
+
+def tx_advance(phase, rate, n: int, chirp=None):
+    """Oscillator state (phase, rate) after n samples."""
+    ph = np.array(phase, dtype=np.uint64)
+    rt = np.array(rate, dtype=np.uint64)
+    ck = _chirp_arg(chirp, ph.size)
+    _load().orc_tx_advance(ph.size, _ptr(ph), _ptr(rt), _ptr(ck), n)
+    return ph, rt

@@ -41,6 +41,10 @@
  * 2^64 and K = (2k/fs^2) 2^64: Eq. 1 is taken as printed, so the
  * instantaneous frequency f0 + 2kt ramps at 2k.  K = 0 is the linear NCO.
  *
+ * Tx (the DAC buffers the GPU generates, Sec. III; chirps, Sec. III.C): the
+ * sum over tones of amplitude times the same table value, rounded to int16
+ * DAC words -- see orc_tx below.
+ *
  * Parity status: every function here is pinned by the CPU tests in
  * tests/test_oracle_pins.py (closed forms, brute force, library routines,
  * invariants); none is "parity unpinned".
@@ -367,4 +371,82 @@ void orc_ddc_points(const int16_t *iq, const double *xc, int64_t S,
                     T, h, D, n, exact_nco, tab, &out[2 * i], &out[2 * i + 1]);
     }
     free(tab);
+}
+
+/* ------------------------------------------------------------------- Tx */
+
+/* Multi-tone transmit synthesis, the DDC's inverse (the GPU produces the
+ * DAC buffers, paper Sec. III; chirped excitations, Sec. III.C): tone t
+ * carries an oscillator state at the buffer's first sample -- phase phi_t,
+ * rate r_t (phase step to the next sample) and second difference K_t -- and
+ * a real amplitude a_t in DAC counts.  Sample j of the buffer is
+ *     v[j] = sum_t a_t * Tab32[(phi_t + j r_t + K_t j(j-1)/2) >> 48]
+ * with Tab32 the FP32 cos/sin table of the DDC (defined through the quarter
+ * wave q[j] = fp32(sin(pi j / 2^15))), and the DAC word is v rounded to the
+ * nearest integer (ties to even) and saturated to int16, I and Q
+ * interleaved.  Because a rounding of floating-point values decides an
+ * integer here, the sum is formed in the FP32 precision of the device, in
+ * ascending tone order, each term a single-rounded FP32 product and each
+ * addition a single-rounded FP32 sum starting from +0.  After the buffer the
+ * state advances by n samples: phi += n r + K n(n-1)/2, r += n K. */
+
+/* The FP32 table by its definition: quadrant g = i >> 14, r = i mod 2^14. */
+void orc_tab32(float *tab)
+{
+    float q[(1 << 14) + 1];
+    for (int j = 0; j <= (1 << 14); ++j) q[j] = (float)sin(3.14159265358979323846 * (double)j / 32768.0);
+    for (int i = 0; i < 65536; ++i) {
+        int g = i >> 14, r = i & 0x3fff;
+        float c = q[(1 << 14) - r], s = q[r];
+        float co, si;
+        switch (g) {
+        case 0: co = c;  si = s;  break;
+        case 1: co = -s; si = c;  break;
+        case 2: co = -c; si = -s; break;
+        default: co = s; si = -c; break;
+        }
+        tab[2 * i] = co;
+        tab[2 * i + 1] = si;
+    }
+}
+
+static int16_t orc_dac(float v)
+{
+    float r = rintf(v);               /* ties to even (default rounding mode) */
+    if (r > 32767.0f) return 32767;
+    if (r < -32768.0f) return -32768;
+    return (int16_t)r;
+}
+
+void orc_tx(int64_t ntones, const uint64_t *phase, const uint64_t *rate,
+            const uint64_t *chirp, const float *amp, int64_t n, int16_t *out)
+{
+    float *tab = (float *)malloc(sizeof(float) * 2 * 65536);
+    orc_tab32(tab);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        float vr = 0.0f, vi = 0.0f;
+        for (int64_t t = 0; t < ntones; ++t) {
+            uint64_t ph = phase[t] + (uint64_t)j * rate[t] + (chirp ? chirp[t] * orc_tri((uint64_t)j) : 0);
+            uint64_t idx = ph >> 48;
+            float pr = amp[t] * tab[2 * idx];
+            float pi = amp[t] * tab[2 * idx + 1];
+            vr = vr + pr;
+            vi = vi + pi;
+        }
+        out[2 * j] = orc_dac(vr);
+        out[2 * j + 1] = orc_dac(vi);
+    }
+    free(tab);
+}
+
+/* Oscillator state after n samples. */
+void orc_tx_advance(int64_t ntones, uint64_t *phase, uint64_t *rate,
+                    const uint64_t *chirp, uint64_t n)
+{
+    for (int64_t t = 0; t < ntones; ++t) {
+        uint64_t K = chirp ? chirp[t] : 0;
+        phase[t] = phase[t] + n * rate[t] + K * orc_tri(n);
+        rate[t] = rate[t] + n * K;
+    }
 }

@@ -430,3 +430,117 @@ def test_pfb_small_workload_end_to_end_properties():
     p = np.mean(np.abs(X) ** 2, axis=0)
     top = sorted(np.argsort(p)[-8:])
     assert top == bins
+
+
+# ------------------------------------------- P18-P22: Tx synthesis (DAC buffers)
+
+def test_p18_tab32_is_the_fp32_table_with_exact_symmetry():
+    t = oracle.tab32().astype(np.float64)
+    i = np.arange(65536)
+    a = 2 * np.pi * i / 65536.0
+    # each entry is the FP32 rounding of the true value (within half an FP32 ulp)
+    assert np.abs(t[:, 0] - np.cos(a)).max() <= 2.0**-25 * 1.0001
+    assert np.abs(t[:, 1] - np.sin(a)).max() <= 2.0**-25 * 1.0001
+    # quarter-turn and half-turn symmetry, exactly
+    assert np.array_equal(t[(i + 16384) % 65536, 0], -t[i, 1])
+    assert np.array_equal(t[(i + 16384) % 65536, 1], t[i, 0])
+    assert np.array_equal(t[(i + 32768) % 65536], -t[i])
+    # the same values as the DDC oracle's FP64 table rounded to FP32, but for rare ties
+    ref = oracle.nco_table()
+    ref32 = np.stack([ref.real, ref.imag], axis=1).astype(np.float32).astype(np.float64)
+    assert np.mean(t == ref32) > 0.999
+
+
+def _tx_numpy(phase, rate, chirp, amp, n):
+    """Independent reference: numpy FP32 scalars, tones in ascending order."""
+    tab = oracle.tab32()
+    out = np.empty(2 * n, dtype=np.int16)
+    for j in range(n):
+        vr = np.float32(0.0)
+        vi = np.float32(0.0)
+        for t in range(len(phase)):
+            tri = j * (j - 1) // 2
+            ph = (int(phase[t]) + j * int(rate[t]) + int(chirp[t]) * tri) % 2**64
+            c = tab[ph >> 48]
+            vr = np.float32(vr + np.float32(np.float32(amp[t]) * c[0]))
+            vi = np.float32(vi + np.float32(np.float32(amp[t]) * c[1]))
+        for k, v in enumerate((vr, vi)):
+            r = np.rint(v)
+            out[2 * j + k] = int(min(max(r, -32768.0), 32767.0))
+    return out
+
+
+def test_p19_tx_matches_independent_fp32_reference():
+    rng = np.random.default_rng(19)
+    nt, n = 6, 400
+    phase = siggen.random_words(rng, nt)
+    rate = siggen.random_words(rng, nt)
+    chirp = siggen.random_words(rng, nt)
+    chirp[:3] = 0
+    amp = rng.uniform(-9000, 9000, nt).astype(np.float32)
+    amp[0] = 30000.0                          # drives some samples into saturation
+    got = oracle.tx(phase, rate, amp, n, chirp=chirp)
+    assert np.array_equal(got, _tx_numpy(phase, rate, chirp, amp, n))
+    assert got.max() == 32767 or got.min() == -32768
+
+
+def test_p20_tx_then_ddc_recovers_the_amplitude():
+    # A tone generated at amplitude A and demodulated with the same oscillator
+    # gives A sum(h) |Tab|^2 plus the DAC rounding error (<= 0.5 LSB per
+    # component): |y - A sum h| <= A 2^-23 sum|h| + sqrt(2)/2 sum|h|.
+    rng = np.random.default_rng(20)
+    T = D = 1024
+    h = siggen.boxcar(D)
+    for A in [100.0, 2345.5, 31000.0]:
+        w = int(siggen.random_words(rng, 1)[0])
+        p0 = int(siggen.random_words(rng, 1)[0])
+        iq = oracle.tx([p0], [w], [A], 8 * D)
+        y = oracle.ddc([w], [p0], h, D, iq=iq)[0]
+        assert y.size == 8
+        assert np.all(np.abs(y - A) <= A * 2.0**-23 + np.sqrt(2) / 2)
+
+
+def test_p21_tx_bin_centred_tones_in_the_spectrum():
+    N = 1024
+    bins = np.array([3, 100, 257, 511, 700, 1000])
+    amps = np.array([4000.0, 100.0, 2500.0, 800.0, 3333.0, 50.0], dtype=np.float32)
+    words = (bins.astype(np.uint64) << np.uint64(54))   # bin k of N = 2^10: k * 2^64 / 2^10
+    iq = oracle.tx(np.zeros(6, np.uint64), words, amps, N)
+    x = iq[0::2].astype(np.float64) + 1j * iq[1::2]
+    X = np.fft.fft(x)
+    # each tone's bin carries N*A (the DAC rounding adds at most N * 0.71 LSB)
+    assert np.all(np.abs(np.abs(X[bins]) - N * amps) <= N * 0.71)
+    rest = np.delete(np.abs(X), bins)
+    assert rest.max() <= N * 0.71
+
+
+def test_p22_tx_buffers_continue_the_waveform():
+    rng = np.random.default_rng(22)
+    nt = 9
+    phase = siggen.random_words(rng, nt)
+    rate = siggen.random_words(rng, nt)
+    chirp = siggen.random_words(rng, nt)
+    amp = rng.uniform(-3000, 3000, nt).astype(np.float32)
+    whole = oracle.tx(phase, rate, amp, 5000, chirp=chirp)
+    parts, ph, rt = [], phase, rate
+    for n in [1, 0, 777, 2, 2220]:
+        parts.append(oracle.tx(ph, rt, amp, n, chirp=chirp))
+        ph, rt = oracle.tx_advance(ph, rt, n, chirp=chirp)
+    parts.append(oracle.tx(ph, rt, amp, 5000 - 3000, chirp=chirp))
+    assert np.array_equal(np.concatenate(parts), whole)
+    # the advanced state is the closed form at sample n
+    ph2, rt2 = oracle.tx_advance(phase, rate, 12345, chirp=chirp)
+    for t in range(nt):
+        assert int(ph2[t]) == oracle.chirp_phase(int(phase[t]), int(rate[t]), int(chirp[t]), 12345)
+        assert int(rt2[t]) == (int(rate[t]) + 12345 * int(chirp[t])) % 2**64
+
+
+def test_p22_tx_chirp_is_demodulated_by_the_chirped_ddc():
+    # Eq. 1 chirp generated as a DAC buffer, demodulated with the same words.
+    inc, K = siggen.chirp_words(-30e6, 9e12)
+    A = 5000.0
+    T, D = 256, 200
+    h = siggen.ddc_lowpass(T, 1e6)
+    iq = oracle.tx([0], [inc], [A], T + 20 * D, chirp=[K])
+    y = oracle.ddc([inc], None, h, D, iq=iq, chirp=[K])[0]
+    assert np.all(np.abs(y - A * h.sum()) <= A * 2.0**-23 * np.abs(h).sum() + np.sqrt(2) / 2 * np.abs(h).sum())
