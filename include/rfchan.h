@@ -201,6 +201,64 @@ int ddc_set_state(rf_ddc_t ddc, const void *blob, size_t size);
 int ddc_reset(rf_ddc_t ddc);
 int ddc_destroy(rf_ddc_t ddc);
 
+/* ============================================================ Tx synthesis
+ *
+ * The transmit buffers (DAC words) the readout generates on the GPU (paper
+ * Sec. III: the transmission-buffer producer; Sec. III.C: chirped
+ * excitations, Eq. 1), the DDC's inverse.  Tone t carries an oscillator
+ * state -- phase phi_t, rate r_t (phase step to the next sample) and second
+ * difference K_t (0 for a fixed tone) -- and an amplitude a_t in DAC counts.
+ * With the state at a buffer's first sample, its sample j is
+ *     v[j] = sum_t a_t * Tab[(phi_t + j r_t + K_t j(j-1)/2) >> 48]
+ * (Tab as for the DDC bank), formed in FP32 in ascending tone order with
+ * every product and every partial sum rounded to FP32 (no fused
+ * multiply-add), then rounded to the nearest integer (ties to even) and
+ * saturated to [-32768, 32767]; I and Q are interleaved int16 as on the
+ * receive side.  After a buffer of n samples the state advances to
+ * phi += n r + K n(n-1)/2, r += n K, so consecutive buffers form one
+ * continuous waveform.  A fixed tone of frequency f has r = round(f/fs 2^64);
+ * an Eq. 1 chirp has the words of ddc_create_chirp.
+ */
+typedef struct rf_tx *rf_tx_t;
+
+/* Create a transmit bank on the current HIP device.
+ *   ntones     1 <= ntones <= 65536.
+ *   phase_inc  host [ntones]: initial rates r_t (copied).
+ *   phase0     host [ntones]: initial phases, or NULL for all zero.
+ *   chirp      host [ntones]: second differences K_t, or NULL (fixed tones;
+ *              the bank then cannot take chirp words later).
+ *   amplitude  host [ntones]: a_t in DAC counts, finite (copied).
+ *   max_samples_per_call  largest nsamples one tx_synthesize accepts.
+ * Returns RF_EINVAL for bad arguments, RF_ENOMEM / RF_EDEVICE on failure. */
+int tx_create(rf_tx_t *out, int32_t ntones, const uint64_t *phase_inc, const uint64_t *phase0,
+              const uint64_t *chirp, const float *amplitude, uint64_t max_samples_per_call);
+
+/* Write the next nsamples of the waveform to out_dev (device, 2*nsamples
+ * int16, 4-byte aligned, owned by the caller and kept live until the stream
+ * reaches the work) and advance the state.  Asynchronous on hip_stream,
+ * ordered after the handle's previous call.  nsamples = 0 does nothing;
+ * nsamples > max_samples_per_call is RF_EINVAL. */
+int tx_synthesize(rf_tx_t tx, int16_t *out_dev, uint64_t nsamples, void *hip_stream);
+
+/* Feedback (paper Sec. III: the buffer generator changes its output in
+ * response to the processed signal): replace the amplitudes, the current
+ * rates and/or the second differences (each array host [ntones], NULL keeps
+ * the current values) from the next sample on; the phase continues without
+ * a jump.  Waits for the handle's last stream.  chirp on a bank created
+ * without chirp words is RF_EINVAL; non-finite amplitudes are RF_EINVAL. */
+int tx_set_tones(rf_tx_t tx, const float *amplitude, const uint64_t *phase_inc, const uint64_t *chirp);
+
+/* Oscillator state at the next sample (host arrays [ntones], each may be
+ * NULL) and the number of samples produced.  Waits for the last stream. */
+int tx_get_state(rf_tx_t tx, uint64_t *phase, uint64_t *rate, uint64_t *samples);
+
+/* Back to the creation state (phases, rates, second differences,
+ * amplitudes, sample count 0). */
+int tx_reset(rf_tx_t tx);
+
+/* Wait for outstanding work and free everything.  NULL is a no-op. */
+int tx_destroy(rf_tx_t tx);
+
 /* ============================================================ Autotuner
  *
  * The paper's handling thread tunes the GPU kernels at run time (Sec. III).

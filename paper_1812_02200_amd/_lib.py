@@ -78,6 +78,12 @@ SIGNATURES = {
     "pfb_destroy": (ctypes.c_int, [_P]),
     "ddc_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32, _P, _I32, _U64]),
     "ddc_create_chirp": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _P, _I32, _P, _I32, _U64]),
+    "tx_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _P, _P, _U64]),
+    "tx_synthesize": (ctypes.c_int, [_P, _P, _U64, _P]),
+    "tx_set_tones": (ctypes.c_int, [_P, _P, _P, _P]),
+    "tx_get_state": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_U64)]),
+    "tx_reset": (ctypes.c_int, [_P]),
+    "tx_destroy": (ctypes.c_int, [_P]),
     "ddc_outputs_for": (_U64, [_P, _U64]),
     "ddc_process": (ctypes.c_int, [_P, _P, _U64, _P, _U64, ctypes.POINTER(_U64), _P]),
     "ddc_get_phase": (ctypes.c_int, [_P, _P]),
@@ -360,6 +366,78 @@ class Ddc:
         if getattr(self, "_h", None):
             h, self._h = self._h, None
             check(lib().ddc_destroy(h), "ddc_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tx:
+    """Multi-tone transmit synthesis handle (tx_* calls): int16 I/Q DAC buffers."""
+
+    def __init__(self, phase_inc, amplitude, phase0=None, chirp=None,
+                 max_samples_per_call: int = 1 << 24):
+        import numpy as np
+        inc = np.ascontiguousarray(np.asarray(phase_inc, dtype=np.uint64).reshape(-1))
+        amp = np.ascontiguousarray(np.asarray(amplitude, dtype=np.float32).reshape(-1))
+        p0 = None if phase0 is None else np.ascontiguousarray(np.asarray(phase0, dtype=np.uint64).reshape(-1))
+        ck = None if chirp is None else np.ascontiguousarray(np.asarray(chirp, dtype=np.uint64).reshape(-1))
+        for name, arr in (("amplitude", amp), ("phase0", p0), ("chirp", ck)):
+            if arr is not None and arr.size != inc.size:
+                raise ValueError("%s must have one entry per tone" % name)
+        self.ntones = int(inc.size)
+        self.max_samples = int(max_samples_per_call)
+        self._h = _P()
+        check(lib().tx_create(ctypes.byref(self._h), self.ntones, inc.ctypes.data,
+                              None if p0 is None else p0.ctypes.data,
+                              None if ck is None else ck.ctypes.data, amp.ctypes.data,
+                              self.max_samples), "tx_create")
+
+    def synthesize(self, n: int, out=None, stream=None):
+        """Next n samples as an int16 tensor [2n] (I/Q interleaved) on the current device."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(2 * max(int(n), 1), dtype=torch.int16, device="cuda")
+        if out.dtype != torch.int16 or not out.is_contiguous() or out.numel() < 2 * n:
+            raise TypeError("out must be a contiguous int16 tensor of >= 2n elements")
+        self.synthesize_ptr(out.data_ptr(), int(n), _stream_handle(stream))
+        return out[: 2 * n]
+
+    def synthesize_ptr(self, out_ptr: int, n: int, stream_handle) -> None:
+        check(lib().tx_synthesize(self._h, out_ptr, int(n), stream_handle), "tx_synthesize")
+
+    def set_tones(self, amplitude=None, phase_inc=None, chirp=None) -> None:
+        import numpy as np
+        arrs = []
+        for arr, dt in ((amplitude, np.float32), (phase_inc, np.uint64), (chirp, np.uint64)):
+            if arr is None:
+                arrs.append(None)
+                continue
+            a = np.ascontiguousarray(np.asarray(arr, dtype=dt).reshape(-1))
+            if a.size != self.ntones:
+                raise ValueError("one entry per tone expected")
+            arrs.append(a)
+        check(lib().tx_set_tones(self._h, *[None if a is None else a.ctypes.data for a in arrs]),
+              "tx_set_tones")
+
+    def state(self):
+        """(phase, rate, samples) at the next sample."""
+        import numpy as np
+        ph = np.empty(self.ntones, dtype=np.uint64)
+        rt = np.empty(self.ntones, dtype=np.uint64)
+        n = _U64(0)
+        check(lib().tx_get_state(self._h, ph.ctypes.data, rt.ctypes.data, ctypes.byref(n)), "tx_get_state")
+        return ph, rt, int(n.value)
+
+    def reset(self) -> None:
+        check(lib().tx_reset(self._h), "tx_reset")
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().tx_destroy(self._h), "tx_destroy")
+            self._h = _P()
 
     def __del__(self):
         try:

@@ -104,4 +104,19 @@ int ddc_default_grid(int ntones, int64_t nout);
 // Number of float entries of the half-wave sine table.
 constexpr int kSinTabLen = 1 << 15;   // floats in the DDC oscillator table (2^14 cos/sin pairs)
 
+// Transmit synthesis (tx_kernels.hip).
+struct TxLaunch {
+    uint32_t *out;          // [n] int16 I/Q pairs (I low half)
+    int64_t n;
+    const uint64_t *phase;  // [ntones] oscillator state at the first sample
+    const uint64_t *rate;
+    const uint64_t *chirp;  // [ntones] second differences, or null
+    const float *amp;       // [ntones] DAC counts
+    const float *halftab;   // 2^15 floats: sin(2 pi i / 2^16), i < 2^15
+    uint64_t *phase_out;    // [ntones] state after the buffer
+    uint64_t *rate_out;
+    int32_t ntones;
+};
+hipError_t launch_tx(const TxLaunch &a, hipStream_t s);
+
 }  // namespace rfk

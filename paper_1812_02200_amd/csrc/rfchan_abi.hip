@@ -1172,3 +1172,219 @@ int ddc_apply_tuned(rf_ddc_t p, uint64_t nsamples)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ Tx
+
+struct rf_tx {
+    int ntones = 0;
+    uint64_t max_samples = 0;
+    int device = 0;
+    // device oscillator state (ping-pong: a call reads cur and writes cur^1)
+    uint64_t *d_phase[2] = {nullptr, nullptr}, *d_rate[2] = {nullptr, nullptr};
+    uint64_t *d_chirp = nullptr;
+    float *d_amp = nullptr, *d_tab = nullptr;
+    int cur = 0;
+    bool chirped = false;
+    uint64_t S = 0;   // samples produced
+    // creation state, for tx_reset
+    uint64_t *h_phase0 = nullptr, *h_rate0 = nullptr, *h_chirp0 = nullptr;
+    float *h_amp0 = nullptr;
+    StreamOrder order;
+};
+
+namespace {
+
+void tx_free(rf_tx *p)
+{
+    if (!p) return;
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(p->d_phase[i]);
+        (void)hipFree(p->d_rate[i]);
+    }
+    (void)hipFree(p->d_chirp);
+    (void)hipFree(p->d_amp);
+    (void)hipFree(p->d_tab);
+    if (p->order.ev) (void)hipEventDestroy(p->order.ev);
+    free(p->h_phase0);
+    free(p->h_rate0);
+    free(p->h_chirp0);
+    free(p->h_amp0);
+    delete p;
+}
+
+// Half-wave sine table S[i] = sin(2 pi i / 2^16), i < 2^15, from the quarter
+// wave q[j] = fp32(sin(pi j / 2^15)) by symmetry.
+void fill_halfwave(float *tab)
+{
+    const double pi = 3.14159265358979323846264338327950288;
+    for (int i = 0; i < rfk::kSinTabLen; ++i) {
+        const int j = i <= (1 << 14) ? i : (1 << 15) - i;
+        tab[i] = (float)sin(pi * (double)j / 32768.0);
+    }
+}
+
+int tx_upload_state(rf_tx *p)
+{
+    const size_t b = sizeof(uint64_t) * p->ntones;
+    HIP_TRY(hipMemcpy(p->d_phase[p->cur], p->h_phase0, b, hipMemcpyHostToDevice), "hipMemcpy(phase)");
+    HIP_TRY(hipMemcpy(p->d_rate[p->cur], p->h_rate0, b, hipMemcpyHostToDevice), "hipMemcpy(rate)");
+    if (p->d_chirp) HIP_TRY(hipMemcpy(p->d_chirp, p->h_chirp0, b, hipMemcpyHostToDevice), "hipMemcpy(chirp)");
+    HIP_TRY(hipMemcpy(p->d_amp, p->h_amp0, sizeof(float) * p->ntones, hipMemcpyHostToDevice), "hipMemcpy(amp)");
+    return RF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tx_create(rf_tx_t *out, int32_t ntones, const uint64_t *phase_inc, const uint64_t *phase0,
+              const uint64_t *chirp, const float *amplitude, uint64_t max_samples_per_call)
+{
+    if (!out) return fail(RF_EINVAL, "tx_create: out is NULL");
+    *out = nullptr;
+    if (ntones < 1 || ntones > 65536) return fail(RF_EINVAL, "tx_create: ntones=%d must be in [1, 65536]", ntones);
+    if (!phase_inc || !amplitude) return fail(RF_EINVAL, "tx_create: phase_inc and amplitude are required");
+    if (max_samples_per_call < 1 || max_samples_per_call > (1ull << 40))
+        return fail(RF_EINVAL, "tx_create: max_samples_per_call out of range");
+    for (int i = 0; i < ntones; ++i)
+        if (!isfinite(amplitude[i])) return fail(RF_EINVAL, "tx_create: amplitude[%d] is not finite", i);
+    rf_tx *p = new (std::nothrow) rf_tx;
+    if (!p) return fail(RF_ENOMEM, "tx_create: host allocation");
+    p->ntones = ntones;
+    p->max_samples = max_samples_per_call;
+    p->chirped = chirp != nullptr;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        tx_free(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    const size_t b = sizeof(uint64_t) * ntones;
+    p->h_phase0 = (uint64_t *)calloc(ntones, sizeof(uint64_t));
+    p->h_rate0 = (uint64_t *)malloc(b);
+    p->h_chirp0 = (uint64_t *)calloc(ntones, sizeof(uint64_t));
+    p->h_amp0 = (float *)malloc(sizeof(float) * ntones);
+    float *tab = (float *)malloc(sizeof(float) * rfk::kSinTabLen);
+    if (!p->h_phase0 || !p->h_rate0 || !p->h_chirp0 || !p->h_amp0 || !tab) {
+        free(tab);
+        tx_free(p);
+        return fail(RF_ENOMEM, "tx_create: host allocation");
+    }
+    if (phase0) memcpy(p->h_phase0, phase0, b);
+    memcpy(p->h_rate0, phase_inc, b);
+    if (chirp) memcpy(p->h_chirp0, chirp, b);
+    memcpy(p->h_amp0, amplitude, sizeof(float) * ntones);
+    fill_halfwave(tab);
+    int rc = RF_OK;
+    if ((rc = dev_alloc(&p->d_phase[0], ntones, "tx phase")) || (rc = dev_alloc(&p->d_phase[1], ntones, "tx phase")) ||
+        (rc = dev_alloc(&p->d_rate[0], ntones, "tx rate")) || (rc = dev_alloc(&p->d_rate[1], ntones, "tx rate")) ||
+        (rc = dev_alloc(&p->d_amp, ntones, "tx amplitude")) || (rc = dev_alloc(&p->d_tab, rfk::kSinTabLen, "tx table")) ||
+        (chirp && (rc = dev_alloc(&p->d_chirp, ntones, "tx chirp")))) {
+        free(tab);
+        tx_free(p);
+        return rc;
+    }
+    e = hipMemcpy(p->d_tab, tab, sizeof(float) * rfk::kSinTabLen, hipMemcpyHostToDevice);
+    free(tab);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        tx_free(p);
+        return hip_fail(e, "tx_create");
+    }
+    if ((rc = tx_upload_state(p))) {
+        tx_free(p);
+        return rc;
+    }
+    *out = p;
+    return RF_OK;
+}
+
+int tx_synthesize(rf_tx_t p, int16_t *out_dev, uint64_t nsamples, void *hip_stream)
+{
+    if (!p) return fail(RF_EINVAL, "tx_synthesize: handle is NULL");
+    if (nsamples > p->max_samples)
+        return fail(RF_EINVAL, "tx_synthesize: nsamples=%llu exceeds max_samples_per_call=%llu",
+                    (unsigned long long)nsamples, (unsigned long long)p->max_samples);
+    if (nsamples == 0) return RF_OK;
+    if (!out_dev) return fail(RF_EINVAL, "tx_synthesize: out_dev is NULL");
+    if ((uintptr_t)out_dev & 3) return fail(RF_EINVAL, "tx_synthesize: out_dev must be 4-byte aligned");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = p->order.before(s);
+    if (rc) return rc;
+    rfk::TxLaunch a{};
+    a.out = (uint32_t *)out_dev;
+    a.n = (int64_t)nsamples;
+    a.phase = p->d_phase[p->cur];
+    a.rate = p->d_rate[p->cur];
+    a.chirp = p->d_chirp;
+    a.amp = p->d_amp;
+    a.halftab = p->d_tab;
+    a.phase_out = p->d_phase[p->cur ^ 1];
+    a.rate_out = p->d_rate[p->cur ^ 1];
+    a.ntones = p->ntones;
+    HIP_TRY(rfk::launch_tx(a, s), "tx kernel launch");
+    p->cur ^= 1;
+    p->S += nsamples;
+    p->order.after(s);
+    return RF_OK;
+}
+
+int tx_set_tones(rf_tx_t p, const float *amplitude, const uint64_t *phase_inc, const uint64_t *chirp)
+{
+    if (!p) return fail(RF_EINVAL, "tx_set_tones: handle is NULL");
+    if (chirp && !p->chirped) return fail(RF_EINVAL, "tx_set_tones: chirp words need a bank created with chirp");
+    if (amplitude)
+        for (int i = 0; i < p->ntones; ++i)
+            if (!isfinite(amplitude[i])) return fail(RF_EINVAL, "tx_set_tones: amplitude[%d] is not finite", i);
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    const size_t b = sizeof(uint64_t) * p->ntones;
+    if (amplitude)
+        HIP_TRY(hipMemcpy(p->d_amp, amplitude, sizeof(float) * p->ntones, hipMemcpyHostToDevice), "hipMemcpy(amp)");
+    if (phase_inc) HIP_TRY(hipMemcpy(p->d_rate[p->cur], phase_inc, b, hipMemcpyHostToDevice), "hipMemcpy(rate)");
+    if (chirp) HIP_TRY(hipMemcpy(p->d_chirp, chirp, b, hipMemcpyHostToDevice), "hipMemcpy(chirp)");
+    return RF_OK;
+}
+
+int tx_get_state(rf_tx_t p, uint64_t *phase, uint64_t *rate, uint64_t *samples)
+{
+    if (!p) return fail(RF_EINVAL, "tx_get_state: handle is NULL");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    const size_t b = sizeof(uint64_t) * p->ntones;
+    if (phase) HIP_TRY(hipMemcpy(phase, p->d_phase[p->cur], b, hipMemcpyDeviceToHost), "hipMemcpy(phase)");
+    if (rate) HIP_TRY(hipMemcpy(rate, p->d_rate[p->cur], b, hipMemcpyDeviceToHost), "hipMemcpy(rate)");
+    if (samples) *samples = p->S;
+    return RF_OK;
+}
+
+int tx_reset(rf_tx_t p)
+{
+    if (!p) return fail(RF_EINVAL, "tx_reset: handle is NULL");
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    int rc = p->order.sync();
+    if (rc) return rc;
+    if ((rc = tx_upload_state(p))) return rc;
+    p->S = 0;
+    return RF_OK;
+}
+
+int tx_destroy(rf_tx_t p)
+{
+    if (!p) return RF_OK;
+    int rc = RF_OK;
+    {
+        DeviceGuard dg(p->device);
+        if (dg.err == hipSuccess) rc = p->order.sync();
+        tx_free(p);
+    }
+    return rc;
+}
+
+}  // extern "C"
