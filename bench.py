@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "pfb", "ddc", "precision", "serving", "copyprobe"])
+                    choices=["all", "pfb", "ddc", "tx", "precision", "serving", "copyprobe"])
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -330,6 +330,67 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     }, (w, d)
 
 
+# -------------------------------------------------------------------- Tx
+
+def bench_tx(rf, torch, siggen, steps, warmup):
+    """1000-tone transmit synthesis (the DDC bank's tones, 8 LSB each), 2^27
+    samples per step in 16 buffers of 2^23; fixed and chirped tones."""
+    w = siggen.ddc_bank()
+    nbuf = w.nsamples // w.buffer
+    amp = np.full(w.words.size, 8.0, dtype=np.float32)
+    out = torch.empty(2 * w.buffer * nbuf, dtype=torch.int16, device="cuda")
+    s = torch.cuda.current_stream()
+    sh = s.cuda_stream
+    res = {"config": {"workload": "tx 1000 tones, 2^27 int16 I/Q samples in 2^23-sample buffers",
+                      "ntones": int(w.words.size), "buffer_samples": w.buffer}}
+    crng = np.random.default_rng(34)
+    cw = [siggen.chirp_words(float(crng.uniform(-90e6, 90e6)), float(crng.uniform(-2e13, 2e13)))
+          for _ in range(w.words.size)]
+    for name, inc, K in (("fixed", w.words, None),
+                         ("chirped", np.array([a for a, _ in cw], np.uint64), np.array([b for _, b in cw], np.uint64))):
+        tx = rf.Tx(inc, amp, w.phase0, K, max_samples_per_call=w.buffer)
+
+        def step():
+            for b in range(nbuf):
+                tx.synthesize_ptr(out.data_ptr() + 4 * b * w.buffer, w.buffer, sh)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            step()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kern_s = ms / 1e3 / (steps * nbuf)
+        # VALU issue: 12.25 (fixed) / 13.7 (chirped) instructions per sample-tone
+        per = 12.25 if K is None else 13.7
+        valu = per * w.words.size * w.buffer / kern_s
+        res[name] = {"value": steps * w.nsamples / (ms / 1e3) / 1e6, "unit": "Msamples/s",
+                     "kernel_us": kern_s * 1e6, "valu_issue_frac": valu / VALU_ISSUE_PEAK}
+        log("tx %s: %.0f Msamples/s, %.1f us/launch" % (name, res[name]["value"], kern_s * 1e6))
+        tx.close()
+    return res, (w, amp)
+
+
+def cpu_tx(oracle, w, amp, budget_s):
+    """The oracle's Tx on the first k samples of the 1000-tone buffer, sized to ~budget_s."""
+    def run(k):
+        t0 = time.perf_counter()
+        oracle.tx(w.phase0, w.words, amp, k)
+        return time.perf_counter() - t0
+    k = 4096
+    t = run(k)
+    for _ in range(2):     # the first probe is dominated by overheads: refine twice
+        k = int(max(k, k * budget_s / max(t, 1e-6)))
+        t = run(k)
+    return {"value": k / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "seconds": t, "sample": "first %d samples of the 1000-tone buffer, FP32 as the kernel, "
+                                    "OpenMP over samples" % k}
+
+
 # ------------------------------------------------------------- precision
 
 MFMA_PEAK_TF = 2500.0          # MI355X dense FP16/BF16 MFMA, published
@@ -489,6 +550,12 @@ def main():
             rec["config"] = r["config"]
             rec["roofline"] = r["roofline"]
         log("ddc: %.0f Msamples/s, %.1f us/launch" % (r["value"], r["kernel_us"]))
+    if a.workload in ("all", "tx"):
+        r, keep["tx"] = bench_tx(rf, torch, siggen, a.steps, a.warmup)
+        rec["tx"] = r
+        if rec["value"] is None:
+            rec["value"] = r["fixed"]["value"]
+            rec["config"] = r["config"]
     if a.workload in ("all", "precision"):
         import oracle
         rec["precision"] = bench_precision(rf, torch, siggen, oracle, max(1, min(a.steps, 5)), 1)
@@ -503,6 +570,12 @@ def main():
             cb = cpu_ddc(oracle, *keep["ddc"], a.cpu_seconds)
             if "cpu_baseline" in rec:
                 rec["ddc"]["cpu_baseline"] = cb
+            else:
+                rec["cpu_baseline"] = cb
+        if "tx" in keep:
+            cb = cpu_tx(oracle, *keep["tx"], a.cpu_seconds / 2)
+            if "cpu_baseline" in rec:
+                rec["tx"]["cpu_baseline"] = cb
             else:
                 rec["cpu_baseline"] = cb
     print(json.dumps(rec))

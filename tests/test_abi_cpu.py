@@ -27,7 +27,8 @@ def declared_functions():
 def test_header_declares_the_documented_calls():
     names = declared_functions()
     for must in ["pfb_create", "pfb_process", "ddc_create", "ddc_process", "rf_strerror",
-                 "pfb_frames_for", "ddc_outputs_for", "ddc_get_phase"]:
+                 "pfb_frames_for", "ddc_outputs_for", "ddc_get_phase", "ddc_create_chirp",
+                 "tx_create", "tx_synthesize", "tx_set_tones", "tx_get_state"]:
         assert must in names
 
 
@@ -91,6 +92,27 @@ def test_ddc_create_rejects_bad_arguments():
     assert not h.value
 
 
+def test_ddc_create_chirp_and_tx_create_reject_bad_arguments():
+    lib = rf.lib()
+    inc = np.arange(4, dtype=np.uint64)
+    K = np.arange(4, dtype=np.uint64)
+    taps = np.ones(8, np.float32)
+    amp = np.ones(4, np.float32)
+    h = ctypes.c_void_p()
+    assert lib.ddc_create_chirp(ctypes.byref(h), 0, inc.ctypes.data, None, K.ctypes.data, 8,
+                                taps.ctypes.data, 2, 10) == rf.RF_EINVAL
+    assert lib.ddc_create_chirp(ctypes.byref(h), 4, None, None, K.ctypes.data, 8,
+                                taps.ctypes.data, 2, 10) == rf.RF_EINVAL
+    assert lib.tx_create(ctypes.byref(h), 0, inc.ctypes.data, None, None, amp.ctypes.data, 10) == rf.RF_EINVAL
+    assert lib.tx_create(ctypes.byref(h), 4, None, None, None, amp.ctypes.data, 10) == rf.RF_EINVAL
+    assert lib.tx_create(ctypes.byref(h), 4, inc.ctypes.data, None, None, None, 10) == rf.RF_EINVAL
+    assert lib.tx_create(ctypes.byref(h), 4, inc.ctypes.data, None, None, amp.ctypes.data, 0) == rf.RF_EINVAL
+    bad = amp.copy()
+    bad[2] = np.inf
+    assert lib.tx_create(ctypes.byref(h), 4, inc.ctypes.data, None, None, bad.ctypes.data, 10) == rf.RF_EINVAL
+    assert not h.value
+
+
 def test_null_handles_are_rejected():
     lib = rf.lib()
     assert lib.pfb_frames_for(None, 100) == 0
@@ -99,6 +121,10 @@ def test_null_handles_are_rejected():
     assert lib.ddc_process(None, None, 0, None, 0, None, None) == rf.RF_EINVAL
     assert lib.pfb_destroy(None) == rf.RF_OK and lib.ddc_destroy(None) == rf.RF_OK
     assert lib.pfb_reset(None) == rf.RF_EINVAL and lib.ddc_reset(None) == rf.RF_EINVAL
+    assert lib.tx_synthesize(None, None, 0, None) == rf.RF_EINVAL
+    assert lib.tx_set_tones(None, None, None, None) == rf.RF_EINVAL
+    assert lib.tx_get_state(None, None, None, None) == rf.RF_EINVAL
+    assert lib.tx_reset(None) == rf.RF_EINVAL and lib.tx_destroy(None) == rf.RF_OK
 
 
 def test_python_binding_raises_instead_of_falling_back():
