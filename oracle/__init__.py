@@ -65,6 +65,7 @@ def _load():
         lib.orc_ddc_noutputs.argtypes = [I, I, I]
         lib.orc_ddc_noutputs.restype = I
         lib.orc_tab32.argtypes = [P]
+        lib.orc_pfb_channels.argtypes = [P, P, I, I, I, P, P, I, P]
         lib.orc_tx.argtypes = [I, P, P, P, P, I, P]
         lib.orc_tx_advance.argtypes = [I, P, P, P, U]
         lib.orc_chirp_phase.argtypes = [U, U, U, U]
@@ -140,6 +141,23 @@ def pfb(h, N: int, M: int, iq=None, x=None, frames=None) -> np.ndarray:
     out = np.empty((nf, N), dtype=np.complex128)
     _load().orc_pfb_frames(_ptr(iqa), _ptr(xc), S, N, M, _ptr(h), _ptr(fr), nf,
                            _ptr(out.view(np.float64)))
+    return out
+
+
+def pfb_channels(h, N: int, M: int, channels, iq=None, x=None) -> np.ndarray:
+    """Selected channels of every valid frame, complex128 [frames x len(channels)],
+    by a direct DFT sum at those bins."""
+    iqa, xc, S = _stream_args(iq, x)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    if h.size != N * M:
+        raise ValueError("prototype length must be N*M")
+    ch = np.ascontiguousarray(channels, dtype=np.int64)
+    if ch.size and (ch.min() < 0 or ch.max() >= N):
+        raise ValueError("channel out of range")
+    nf = pfb_nframes(S, N, M)
+    out = np.empty((nf, ch.size), dtype=np.complex128)
+    _load().orc_pfb_channels(_ptr(iqa), _ptr(xc), S, N, M, _ptr(h), _ptr(ch), ch.size,
+                             _ptr(out.view(np.float64)))
     return out
 
 

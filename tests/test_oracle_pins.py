@@ -544,3 +544,20 @@ def test_p22_tx_chirp_is_demodulated_by_the_chirped_ddc():
     iq = oracle.tx([0], [inc], [A], T + 20 * D, chirp=[K])
     y = oracle.ddc([inc], None, h, D, iq=iq, chirp=[K])[0]
     assert np.all(np.abs(y - A * h.sum()) <= A * 2.0**-23 * np.abs(h).sum() + np.sqrt(2) / 2 * np.abs(h).sum())
+
+
+# ----------------------------------------------- P23: selected channels (Sec. III.A)
+
+@pytest.mark.parametrize("N,M", [(16, 4), (64, 8), (256, 2)])
+def test_p23_selected_channels_equal_the_full_spectrum_columns(N, M):
+    # the direct evaluation at chosen bins agrees with the FFT path's columns
+    rng = np.random.default_rng(N + M)
+    h = siggen.pfb_prototype(N, M, "kaiser", 9.0)
+    iq = siggen.quantize(rng.normal(0, 2000, 40 * N) + 1j * rng.normal(0, 2000, 40 * N))
+    chans = rng.choice(N, size=min(N, 11), replace=False)
+    chans = np.concatenate([chans, [0, N - 1, N // 2]])
+    chans = np.unique(chans)[rng.permutation(np.unique(chans).size)]
+    full = oracle.pfb(h, N, M, iq=iq)
+    sub = oracle.pfb_channels(h, N, M, chans, iq=iq)
+    assert sub.shape == (full.shape[0], chans.size)
+    assert np.allclose(sub, full[:, chans], rtol=0, atol=1e-9 * np.abs(full).max())
