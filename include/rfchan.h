@@ -91,12 +91,26 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto,
  * pure host-side function of the handle's sample count (no device sync). */
 uint64_t pfb_frames_for(rf_pfb_t pfb, uint64_t nsamples);
 
+/* Choose the channels pfb_process returns (paper Sec. III.A: the full
+ * spectrum or specific user-defined channels).  channels: host [nsel]
+ * distinct bins in [0, N) in the order wanted; after this call every frame
+ * is written as nsel complex values, frame f's value for channels[c] at
+ * out_dev[f*nsel + c] -- bit-identical to the same bin of the full spectrum
+ * (the transform is the same; only the chosen bins are stored).  nsel = 0
+ * (channels may be NULL) returns to all N bins in natural order.  Frame
+ * counts, history and state are unaffected.  RF_EINVAL for a bin out of
+ * range or repeated; RF_EUNSUPPORTED for the MFMA DFT modes.  Waits for the
+ * handle's last stream. */
+int pfb_set_channels(rf_pfb_t pfb, const int32_t *channels, int32_t nsel);
+
 /* Channelize the next `nsamples` samples of the stream.
  *   iq_dev          device pointer, 2*nsamples int16 (may be NULL if nsamples == 0).
  *   nsamples        any value from 0 to max_samples_per_call, including < N.
  *   out_dev         device pointer to out_cap_frames * N complex64 values; frame
- *                   f of this call is written at out_dev + 2*N*f (frame-major).
- *   out_cap_frames  capacity in frames; RF_ECAPACITY if < pfb_frames_for().
+ *                   f of this call is written at out_dev + 2*N*f (frame-major;
+ *                   N becomes nsel after pfb_set_channels).
+ *   out_cap_frames  capacity in frames (of N values, or of nsel values after
+ *                   pfb_set_channels); RF_ECAPACITY if < pfb_frames_for().
  *   frames_out      host pointer (may be NULL): number of frames written.
  *   hip_stream      hipStream_t to enqueue on.
  * Enqueues one kernel; returns without waiting for it. */

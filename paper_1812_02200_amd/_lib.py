@@ -78,6 +78,7 @@ SIGNATURES = {
     "pfb_destroy": (ctypes.c_int, [_P]),
     "ddc_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32, _P, _I32, _U64]),
     "ddc_create_chirp": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _P, _I32, _P, _I32, _U64]),
+    "pfb_set_channels": (ctypes.c_int, [_P, _P, _I32]),
     "tx_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _P, _P, _U64]),
     "tx_synthesize": (ctypes.c_int, [_P, _P, _U64, _P]),
     "tx_set_tones": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -190,24 +191,37 @@ class Pfb:
         check(lib().pfb_create(ctypes.byref(self._h), self.N, self.M, h.ctypes.data, int(dft_mode),
                                int(max_samples_per_call)), "pfb_create")
         self.max_samples = int(max_samples_per_call)
+        self.width = self.N            # values per output frame (N, or the chosen channels)
 
     def frames_for(self, nsamples: int) -> int:
         return int(lib().pfb_frames_for(self._h, int(nsamples)))
 
+    def set_channels(self, channels=None) -> None:
+        """Return only these bins (in this order) from now on; None: all N bins."""
+        import numpy as np
+        if channels is None:
+            check(lib().pfb_set_channels(self._h, None, 0), "pfb_set_channels")
+            self.width = self.N
+            return
+        ch = np.ascontiguousarray(np.asarray(channels, dtype=np.int32).reshape(-1))
+        check(lib().pfb_set_channels(self._h, ch.ctypes.data if ch.size else None, int(ch.size)),
+              "pfb_set_channels")
+        self.width = int(ch.size) if ch.size else self.N
+
     def process(self, iq, out=None, stream=None):
-        """Channelize int16 I/Q tensor `iq`; returns a complex64 tensor [frames, N]."""
+        """Channelize int16 I/Q tensor `iq`; returns a complex64 tensor [frames, width]."""
         torch = _torch()
         n = _check_iq(iq)
         F = self.frames_for(n)
         if out is None:
-            out = torch.empty((max(F, 1), self.N), dtype=torch.complex64, device=iq.device)
+            out = torch.empty((max(F, 1), self.width), dtype=torch.complex64, device=iq.device)
         if out.dtype != torch.complex64 or not out.is_contiguous():
             raise TypeError("out must be a contiguous complex64 tensor")
-        cap = out.numel() // self.N
+        cap = out.numel() // self.width
         got = _U64(0)
         check(lib().pfb_process(self._h, iq.data_ptr() if n else None, n, out.data_ptr(), cap,
                                 ctypes.byref(got), _stream_handle(stream)), "pfb_process")
-        return out.view(-1, self.N)[: got.value]
+        return out.view(-1, self.width)[: got.value]
 
     def process_ptr(self, iq_ptr: int, nsamples: int, out_ptr: int, out_cap_frames: int,
                     stream_handle: int) -> int:

@@ -27,6 +27,8 @@ struct PfbLaunch {
     int32_t run_len;        // frames per lane-group run (multiple of 4)
     int32_t N, M;
     int32_t variant;        // kernel variant bits (0: default)
+    const int32_t *sel;     // [N] bin -> output column (-1: not written), or null for all bins
+    int32_t nsel;           // output row length when sel is set
 };
 
 struct DdcLaunch {

@@ -140,6 +140,8 @@ struct rf_pfb {
     int64_t H = 0;         // retained samples (virtual stream starts at frames*N)
     int run_len = 0;       // 0: heuristic
     int variant = 0;       // kernel variant bits
+    int32_t *d_sel = nullptr;   // [N] bin -> output column or -1 (chosen channels)
+    int nsel = 0;               // 0: every bin
     StreamOrder order;
 };
 
@@ -161,6 +163,7 @@ void pfb_free(rf_pfb *p)
     (void)hipFree(p->d_tw);
     (void)hipFree(p->d_hist[0]);
     (void)hipFree(p->d_hist[1]);
+    (void)hipFree(p->d_sel);
     if (p->order.ev) (void)hipEventDestroy(p->order.ev);
     delete p;
 }
@@ -209,6 +212,8 @@ int pfb_prepare(rf_pfb *p, const int16_t *iq_dev, uint64_t nsamples, float *out_
     a->N = p->N;
     a->M = p->M;
     a->variant = p->variant;
+    a->sel = p->nsel > 0 ? p->d_sel : nullptr;
+    a->nsel = p->nsel;
     *frames = F;
     return RF_OK;
 }
@@ -319,6 +324,41 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
     const char *vr = getenv("RFCHAN_PFB_VARIANT");
     if (vr) p->variant = atoi(vr);
     *out = p;
+    return RF_OK;
+}
+
+int pfb_set_channels(rf_pfb_t p, const int32_t *channels, int32_t nsel)
+{
+    if (!p) return fail(RF_EINVAL, "pfb_set_channels: handle is NULL");
+    if (nsel < 0 || nsel > p->N) return fail(RF_EINVAL, "pfb_set_channels: nsel=%d must be in [0, N]", nsel);
+    if (nsel > 0 && !channels) return fail(RF_EINVAL, "pfb_set_channels: channels is NULL");
+    if (nsel > 0 && p->mode != RF_DFT_FFT_F32)
+        return fail(RF_EUNSUPPORTED, "pfb_set_channels: chosen channels need the FP32 FFT mode");
+    int32_t *map = (int32_t *)malloc(sizeof(int32_t) * p->N);
+    if (!map) return fail(RF_ENOMEM, "pfb_set_channels: host allocation");
+    for (int k = 0; k < p->N; ++k) map[k] = -1;
+    for (int c = 0; c < nsel; ++c) {
+        const int32_t k = channels[c];
+        if (k < 0 || k >= p->N || map[k] >= 0) {
+            free(map);
+            return fail(RF_EINVAL, "pfb_set_channels: channel %d is out of range or repeated", (int)k);
+        }
+        map[k] = c;
+    }
+    DeviceGuard dg(p->device);
+    if (dg.err != hipSuccess) {
+        free(map);
+        return hip_fail(dg.err, "hipSetDevice");
+    }
+    int rc = p->order.sync();
+    if (rc == RF_OK && nsel > 0 && !p->d_sel) rc = dev_alloc(&p->d_sel, (size_t)p->N, "channel map");
+    if (rc == RF_OK && nsel > 0) {
+        const hipError_t e = hipMemcpy(p->d_sel, map, sizeof(int32_t) * p->N, hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(channel map)");
+    }
+    free(map);
+    if (rc) return rc;
+    p->nsel = nsel;
     return RF_OK;
 }
 

@@ -54,13 +54,13 @@ def run_pfb(pfb, iq_dev, sizes, torch):
     pos = 0
     for n in sizes:
         F = pfb.frames_for(n)
-        out = torch.empty((max(F, 1), pfb.N), dtype=torch.complex64, device="cuda")
+        out = torch.empty((max(F, 1), pfb.width), dtype=torch.complex64, device="cuda")
         y = pfb.process(iq_dev[2 * pos: 2 * (pos + n)], out=out)
         assert y.shape[0] == F
         outs.append(y)
         pos += n
     torch.cuda.synchronize()
-    return torch.cat(outs, 0).cpu().numpy() if outs else np.zeros((0, pfb.N), np.complex64)
+    return torch.cat(outs, 0).cpu().numpy() if outs else np.zeros((0, pfb.width), np.complex64)
 
 
 def run_ddc(ddc, iq_dev, sizes, torch):
