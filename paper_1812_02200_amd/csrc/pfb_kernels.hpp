@@ -17,8 +17,9 @@
 //  * The remaining passes are radix-16 (radix 8/4/2 for the last one) Stockham
 //    passes: a team of N/16 threads owns one frame, every thread holds 16 points
 //    per pass.  The last pass writes the natural-order spectrum straight to HBM
-//    -- or, when the caller chose a set of channels, only those bins, each to
-//    its column (same arithmetic, fewer bytes written).
+//    -- or, when the caller chose a set of channels, back to LDS, from where
+//    the frame's team gathers the chosen bins into consecutive columns (same
+//    arithmetic, fewer bytes written).
 //  * LDS holds the frames of one phase, indexed with one float2 of padding per
 //    64 entries (i + 4*(i>>6)) so the strided stores of the Ns = 4 pass hit
 //    distinct banks.  Pass twiddles are staged in LDS as [r][k] tables so that
@@ -32,7 +33,8 @@
 //
 // Variant bits (kernel template parameter V, chosen at launch):
 //   1: two LDS phase buffers, one work-group barrier per phase (N <= 1024);
-//   2: ordinary (write-back) stores instead of non-temporal stores.
+//   2: ordinary (write-back) stores instead of non-temporal stores;
+//   8: only chosen channels are stored (bin list in PfbLaunch::sel).
 #pragma once
 #include "fft_device.hpp"
 #include "rf_internal.hpp"
@@ -148,9 +150,9 @@ __device__ __forceinline__ void load_block(const VStream &vs, int64_t vlen, int6
 
 // One Stockham pass of radix R and stride NS over the frame at `fb` (LDS,
 // unpadded frame base).  Thread `tl` of the frame's team handles butterflies
-// j = tl + b*NT.  The last pass stores to `outf` (global, frame base): bin k
-// at column k, or at column sel[k] when a channel map is given (-1: skip).
-template <int N, int R, int NS, bool LAST, bool NT_STORE>
+// j = tl + b*NT.  The last pass stores to `outf` (global, frame base), or,
+// with SEL (chosen channels), back to LDS in natural bin order.
+template <int N, int R, int NS, bool LAST, bool NT_STORE, bool SEL>
 __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
                                          const cf *__restrict__ twg, float *__restrict__ outf,
                                          bool valid, const int32_t *__restrict__ sel)
@@ -189,20 +191,16 @@ __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
         }
         dft<R>(v[b]);
         const int idxD = (j / NS) * NS * R + k;
-        if constexpr (LAST) {
+        if constexpr (LAST && !SEL) {
             if (valid) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     f2v o = {v[b][r].x, v[b][r].y};
-                    int pos = idxD + r * NS;            // bin, natural order
-                    if (sel) pos = sel[pos];            // its column among the chosen channels
-                    if (pos >= 0) {
-                        f2v *dst = (f2v *)(outf + 2 * pos);
-                        if constexpr (NT_STORE)
-                            __builtin_nontemporal_store(o, dst);
-                        else
-                            *dst = o;
-                    }
+                    f2v *dst = (f2v *)(outf + 2 * (idxD + r * NS));
+                    if constexpr (NT_STORE)
+                        __builtin_nontemporal_store(o, dst);
+                    else
+                        *dst = o;
                 }
             }
         } else {
@@ -213,15 +211,30 @@ __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
     if constexpr (!LAST) group_sync<XW>();
 }
 
-template <int N, int NS, bool NT_STORE>
+template <int N, int NS, bool NT_STORE, bool SEL>
 __device__ __forceinline__ void fft_passes(cf *lds, int fb, int tl, const cf *twl,
                                            const cf *__restrict__ twg, float *__restrict__ outf,
-                                           bool valid, const int32_t *__restrict__ sel)
+                                           bool valid, const int32_t *__restrict__ sel, int nsel)
 {
     if constexpr (NS < N) {
         constexpr int R = pass_radix(N, NS);
-        fft_pass<N, R, NS, NS * R == N, NT_STORE>(lds, fb, tl, twl, twg, outf, valid, sel);
-        fft_passes<N, NS * R, NT_STORE>(lds, fb, tl, twl, twg, outf, valid, sel);
+        fft_pass<N, R, NS, NS * R == N, NT_STORE, SEL>(lds, fb, tl, twl, twg, outf, valid, sel);
+        fft_passes<N, NS * R, NT_STORE, SEL>(lds, fb, tl, twl, twg, outf, valid, sel, nsel);
+    } else if constexpr (SEL) {
+        // the spectrum is in LDS: the team gathers the chosen bins into
+        // consecutive columns (sel = the bins, in output order)
+        group_sync<!PfbPlan<N>::TEAM_IN_WAVE>();
+        if (valid) {
+            for (int c = tl; c < nsel; c += PfbPlan<N>::NT) {
+                const cf x = lds[lpad(fb + sel[c])];
+                f2v o = {x.x, x.y};
+                f2v *dst = (f2v *)(outf + 2 * c);
+                if constexpr (NT_STORE)
+                    __builtin_nontemporal_store(o, dst);
+                else
+                    *dst = o;
+            }
+        }
     }
 }
 
@@ -330,8 +343,11 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     const int64_t F = a.F;
     const int RL = a.run_len;
     const int nph = RL >> 2;
-    // output row length: all N bins, or the chosen channels (a.sel maps bin -> column or -1)
-    const int64_t ldo = a.sel ? (int64_t)a.nsel : (int64_t)N;
+    // output row length: all N bins, or the chosen channels (variant bit 8:
+    // a.sel lists the bins in output order; compiled only into that variant)
+    constexpr bool SEL = (V & 8) != 0;
+    const int32_t *sel = SEL ? a.sel : nullptr;
+    const int64_t ldo = SEL ? (int64_t)a.nsel : (int64_t)N;
 
     const int g = tid / L;
     const int c = tid - g * L;
@@ -377,8 +393,8 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             }
             fir_phase<N, M>(st, lds, g, c);
             group_sync<!P::LG_IN_WAVE>();
-            fft_passes<N, 4, VV::NT_STORE>(lds, slot * N, tl, twl, twg,
-                                           a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, a.sel);
+            fft_passes<N, 4, VV::NT_STORE, SEL>(lds, slot * N, tl, twl, twg,
+                                           a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, sel, a.nsel);
             if constexpr (SYNC2) group_sync<true>();
             else wave_fence();
             if (more) shift_window<N, M>(st, pre);
@@ -416,8 +432,8 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             {
                 const int64_t f = f0t + 4 * ph + q2;
                 const bool valid = f < f1t;
-                fft_passes<N, 4, VV::NT_STORE>(lds, slot * N, tl, twl, twg,
-                                               a.out + 2 * (valid ? f : 0) * ldo, valid, a.sel);
+                fft_passes<N, 4, VV::NT_STORE, SEL>(lds, slot * N, tl, twl, twg,
+                                               a.out + 2 * (valid ? f : 0) * ldo, valid, sel, a.nsel);
             }
             if constexpr (SYNC2) group_sync<true>();
             else wave_fence();

@@ -1,4 +1,5 @@
-// Instantiations of the fused PFB kernel for N = 1024 (M = 1..16), plus the
+// Instantiations of the fused PFB kernel for N = 1024 (M = 1..16), all bins or
+// chosen channels. plus the
 // tunable variants of the M = 8 kernel (double-buffered LDS, store type).
 #include "pfb_kernels.hpp"
 
@@ -6,6 +7,7 @@ namespace rfk {
 
 hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s)
 {
+    if (a.sel) return launch_pfb_nv<1024, 8>(a, s);
     if (a.M == 8) {
         switch (a.variant) {
         case 1: return launch_pfb_nmv<1024, 8, 1>(a, s);

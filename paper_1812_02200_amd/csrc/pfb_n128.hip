@@ -1,9 +1,14 @@
-// Instantiations of the fused PFB kernel for N = 128 (M = 1..16).
+// Instantiations of the fused PFB kernel for N = 128 (M = 1..16), all bins or
+// chosen channels.
 #include "pfb_kernels.hpp"
 
 namespace rfk {
 
-hipError_t launch_pfb_n128(const PfbLaunch &a, hipStream_t s) { return launch_pfb_nv<128, 0>(a, s); }
+hipError_t launch_pfb_n128(const PfbLaunch &a, hipStream_t s)
+{
+    if (a.sel) return launch_pfb_nv<128, 8>(a, s);
+    return launch_pfb_nv<128, 0>(a, s);
+}
 
 hipError_t launch_pfb_group_n128(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
 {

@@ -27,7 +27,7 @@ struct PfbLaunch {
     int32_t run_len;        // frames per lane-group run (multiple of 4)
     int32_t N, M;
     int32_t variant;        // kernel variant bits (0: default)
-    const int32_t *sel;     // [N] bin -> output column (-1: not written), or null for all bins
+    const int32_t *sel;     // [nsel] chosen bins in output order, or null for all N bins
     int32_t nsel;           // output row length when sel is set
 };
 

@@ -140,7 +140,7 @@ struct rf_pfb {
     int64_t H = 0;         // retained samples (virtual stream starts at frames*N)
     int run_len = 0;       // 0: heuristic
     int variant = 0;       // kernel variant bits
-    int32_t *d_sel = nullptr;   // [N] bin -> output column or -1 (chosen channels)
+    int32_t *d_sel = nullptr;   // [N] capacity: chosen bins in output order
     int nsel = 0;               // 0: every bin
     StreamOrder order;
 };
@@ -353,7 +353,7 @@ int pfb_set_channels(rf_pfb_t p, const int32_t *channels, int32_t nsel)
     int rc = p->order.sync();
     if (rc == RF_OK && nsel > 0 && !p->d_sel) rc = dev_alloc(&p->d_sel, (size_t)p->N, "channel map");
     if (rc == RF_OK && nsel > 0) {
-        const hipError_t e = hipMemcpy(p->d_sel, map, sizeof(int32_t) * p->N, hipMemcpyHostToDevice);
+        const hipError_t e = hipMemcpy(p->d_sel, channels, sizeof(int32_t) * nsel, hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(channel map)");
     }
     free(map);
