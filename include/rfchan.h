@@ -73,7 +73,12 @@ typedef struct rf_pfb *rf_pfb_t;
 
 /* Create a channelizer on the current HIP device.
  *   out       receives the handle.
- *   nchan     N: a power of two, 16 <= N <= 4096.
+ *   nchan     N: a power of two, 16 <= N <= 4096 (one fused kernel per buffer),
+ *             or any N in [16, 2^24] whose only prime factors are 2, 3 and 5 and
+ *             that splits into two factors <= 4096 -- e.g. the 10^5 channels of
+ *             Sec. III.A, Fig. 3 -- (a fold pass and a four-step FFT through
+ *             device scratch of 2 x (max_samples_per_call/N + 2) frames; FP32 FFT
+ *             mode only; no chosen channels, no tuning, not served).
  *   ntaps     M: 1 <= M <= 16.
  *   proto     host array of N*M FP32 prototype taps h[0..N*M); copied, the
  *             caller may free it on return.

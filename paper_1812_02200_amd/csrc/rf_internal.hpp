@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fft_device.hpp"
+
 namespace rfk {
 
 // Virtual stream seen by one process call: `hist` (H retained samples) followed
@@ -105,6 +107,35 @@ int ddc_default_grid(int ntones, int64_t nout);
 
 // Number of float entries of the half-wave sine table.
 constexpr int kSinTabLen = 1 << 15;   // floats in the DDC oscillator table (2^14 cos/sin pairs)
+
+// PFB for large or non-power-of-two N (pfb_large.hip).
+struct LargePlan {
+    int64_t N = 0;
+    int N1 = 0, N2 = 1;      // N = N1 * N2, each <= 4096 (N2 = 1: one step)
+    int nr1 = 0, nr2 = 0;    // radices of the two transform lengths
+    int rad1[16] = {}, rad2[16] = {};
+};
+struct LargeBuffers {
+    cf *v = nullptr;         // folded frames [frames x N]
+    cf *y = nullptr;         // first-step output [frames x N]
+    const float *tables = nullptr;   // W_N1^j, W_N2^j, then the two W_N tables
+};
+struct StepDesc {
+    int L, nr, TB;
+    int rad[16];
+    const cf *tw;            // W_L^j
+    int64_t C;               // transforms per frame
+    int64_t in_cs, in_es, out_cs, out_es;
+    const cf *thi, *tlo;     // four-step twiddle W_N^e = thi[e >> tsh] * tlo[e mod 2^tsh], or null
+    int tsh;
+    const cf *src;
+    cf *dst;
+};
+bool large_plan(int64_t N, LargePlan *pl);
+bool large_supported(int64_t N);
+size_t large_table_floats(const LargePlan &pl);
+void large_table_fill(const LargePlan &pl, float *t);
+hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const LargeBuffers &b, hipStream_t s);
 
 // Transmit synthesis (tx_kernels.hip).
 struct TxLaunch {

@@ -142,6 +142,12 @@ struct rf_pfb {
     int variant = 0;       // kernel variant bits
     int32_t *d_sel = nullptr;   // [N] capacity: chosen bins in output order
     int nsel = 0;               // 0: every bin
+    // large or non-power-of-two N: separate fold and four-step FFT passes
+    bool large = false;
+    rfk::LargePlan lplan;
+    rfk::LargeBuffers lbuf;
+    float *d_ltab = nullptr;
+    rfk::cf *d_lv = nullptr, *d_ly = nullptr;
     StreamOrder order;
 };
 
@@ -164,6 +170,9 @@ void pfb_free(rf_pfb *p)
     (void)hipFree(p->d_hist[0]);
     (void)hipFree(p->d_hist[1]);
     (void)hipFree(p->d_sel);
+    (void)hipFree(p->d_ltab);
+    (void)hipFree(p->d_lv);
+    (void)hipFree(p->d_ly);
     if (p->order.ev) (void)hipEventDestroy(p->order.ev);
     delete p;
 }
@@ -264,8 +273,13 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
 {
     if (!out) return fail(RF_EINVAL, "pfb_create: out is NULL");
     *out = nullptr;
-    if (nchan < 16 || nchan > 4096 || (nchan & (nchan - 1)))
-        return fail(RF_EINVAL, "pfb_create: nchan=%d must be a power of two in [16, 4096]", nchan);
+    const bool fused = nchan >= 16 && nchan <= 4096 && !(nchan & (nchan - 1));
+    if (!fused && !rfk::large_supported(nchan))
+        return fail(RF_EINVAL,
+                    "pfb_create: nchan=%d must be a power of two in [16, 4096] or a product of "
+                    "powers of 2, 3 and 5 in [16, 2^24] splitting into two factors <= 4096", nchan);
+    if (!fused && dft_mode != RF_DFT_FFT_F32)
+        return fail(RF_EUNSUPPORTED, "pfb_create: large or non-power-of-two nchan needs the FP32 FFT mode");
     if (ntaps < 1 || ntaps > 16) return fail(RF_EINVAL, "pfb_create: ntaps=%d must be in [1, 16]", ntaps);
     if (!proto) return fail(RF_EINVAL, "pfb_create: proto is NULL");
     if (max_samples_per_call < 1 || max_samples_per_call > (1ull << 40))
@@ -290,6 +304,39 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         return hip_fail(e, "hipGetDevice");
     }
     const size_t span = (size_t)nchan * ntaps;
+    if (!fused) {
+        p->large = true;
+        rfk::large_plan(nchan, &p->lplan);
+        const size_t nt = rfk::large_table_floats(p->lplan);
+        const size_t fcap = max_samples_per_call / (uint64_t)nchan + 2;   // frames one call can emit
+        float *tab = (float *)malloc(sizeof(float) * nt);
+        if (!tab) {
+            pfb_free(p);
+            return fail(RF_ENOMEM, "pfb_create: host allocation");
+        }
+        rfk::large_table_fill(p->lplan, tab);
+        if ((rc = dev_alloc(&p->d_taps, span, "taps")) || (rc = dev_alloc(&p->d_ltab, nt, "twiddles")) ||
+            (rc = dev_alloc(&p->d_hist[0], span, "history")) || (rc = dev_alloc(&p->d_hist[1], span, "history")) ||
+            (rc = dev_alloc(&p->d_lv, fcap * nchan, "fold scratch")) ||
+            (rc = dev_alloc(&p->d_ly, fcap * nchan, "FFT scratch"))) {
+            free(tab);
+            pfb_free(p);
+            return rc;
+        }
+        e = hipMemcpy(p->d_taps, proto, span * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->d_ltab, tab, sizeof(float) * nt, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);
+        free(tab);
+        if (e != hipSuccess) {
+            pfb_free(p);
+            return hip_fail(e, "pfb_create");
+        }
+        p->lbuf.v = p->d_lv;
+        p->lbuf.y = p->d_ly;
+        p->lbuf.tables = p->d_ltab;
+        *out = p;
+        return RF_OK;
+    }
     // FFT: pass twiddle tables (float pairs); MFMA: DFT16 block matrix + W256 twiddles
     const int ntw = dft_mode == RF_DFT_FFT_F32 ? rfk::pfb_twiddle_count(nchan)
                                                : (rfk::pfb_mfma_table_floats() + 1) / 2;
@@ -332,8 +379,9 @@ int pfb_set_channels(rf_pfb_t p, const int32_t *channels, int32_t nsel)
     if (!p) return fail(RF_EINVAL, "pfb_set_channels: handle is NULL");
     if (nsel < 0 || nsel > p->N) return fail(RF_EINVAL, "pfb_set_channels: nsel=%d must be in [0, N]", nsel);
     if (nsel > 0 && !channels) return fail(RF_EINVAL, "pfb_set_channels: channels is NULL");
-    if (nsel > 0 && p->mode != RF_DFT_FFT_F32)
-        return fail(RF_EUNSUPPORTED, "pfb_set_channels: chosen channels need the FP32 FFT mode");
+    if (nsel > 0 && (p->mode != RF_DFT_FFT_F32 || p->large))
+        return fail(RF_EUNSUPPORTED,
+                    "pfb_set_channels: chosen channels need the FP32 FFT mode and a power-of-two N <= 4096");
     int32_t *map = (int32_t *)malloc(sizeof(int32_t) * p->N);
     if (!map) return fail(RF_ENOMEM, "pfb_set_channels: host allocation");
     for (int k = 0; k < p->N; ++k) map[k] = -1;
@@ -382,7 +430,9 @@ int pfb_process(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out
     hipStream_t s = (hipStream_t)hip_stream;
     rc = p->order.before(s);
     if (rc) return rc;
-    if (p->mode == RF_DFT_FFT_F32)
+    if (p->large)
+        HIP_TRY(rfk::launch_pfb_large(a, p->lplan, p->lbuf, s), "pfb large-N launch");
+    else if (p->mode == RF_DFT_FFT_F32)
         HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
     else
         HIP_TRY(rfk::launch_pfb_mfma(a, p->mode == RF_DFT_MFMA_BF16X2 ? rfk::RF_PREC_BF16 : rfk::RF_PREC_F16, s),
@@ -1026,6 +1076,7 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
 {
     if (!p || nsamples < (uint64_t)p->N * p->M || nsamples > p->max_samples)
         return fail(RF_EINVAL, "pfb_tune: need a handle and N*M <= nsamples <= max_samples_per_call");
+    if (p->large) return fail(RF_EUNSUPPORTED, "pfb_tune: large-N banks have no tunable launch shape");
     DeviceGuard dg(p->device);
     HIP_TRY(dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;

@@ -543,6 +543,8 @@ int rfs_open_stream(rfs_t S, const rfs_stream_desc *d, int32_t *id)
     if (!(d->kinds & (RFS_PFB | RFS_DDC)) || (d->kinds & ~(RFS_PFB | RFS_DDC)))
         return set_error(RF_EINVAL, "rfs_open_stream: kinds must be RFS_PFB and/or RFS_DDC");
     if (d->max_buffer < 1) return set_error(RF_EINVAL, "rfs_open_stream: max_buffer must be >= 1");
+    if ((d->kinds & RFS_PFB) && (d->nchan < 16 || d->nchan > 4096 || (d->nchan & (d->nchan - 1))))
+        return set_error(RF_EINVAL, "rfs_open_stream: served PFB streams need a power-of-two nchan in [16, 4096]");
     const size_t fp = footprint_of(d);
     {
         std::lock_guard<std::mutex> lk(S->mu);

@@ -61,11 +61,25 @@ def _pfb_create(N, M, proto, mode=0, maxs=1024):
     return st, h
 
 
-@pytest.mark.parametrize("N,M", [(100, 4), (8, 4), (8192, 2), (64, 0), (64, 17), (0, 1)])
+# 1001 = 7 * 11 * 13 and 4097 = 17 * 241 have other prime factors; 2^25 is too
+# large; 3^15 has no split into two factors <= 4096.
+@pytest.mark.parametrize("N,M", [(1001, 4), (8, 4), (4097, 1), (1 << 25, 1), (3 ** 15, 1),
+                                 (64, 0), (64, 17), (0, 1)])
 def test_pfb_create_rejects_bad_shapes(N, M):
-    st, h = _pfb_create(N, M, np.zeros(max(N * M, 1)))
+    st, h = _pfb_create(N, M, np.zeros(max(min(N * M, 1 << 20), 1)))
     assert st == rf.RF_EINVAL and not h.value
     assert rf.lib().rf_last_error()
+
+
+def test_large_n_split_rules():
+    # products of 2, 3 and 5 up to 2^24 that split into two factors <= 4096
+    # are accepted by the validation (creation then needs a device)
+    for N in (100, 1000, 6000, 100000, 10**6, 10**7, 8192, 1 << 24):
+        st, h = _pfb_create(N, 2, np.zeros(2 * N))
+        assert st != rf.RF_EINVAL, N
+    for N, mode in ((1000, rf.RF_DFT_MFMA_F16X2), (100000, rf.RF_DFT_MFMA_BF16X2)):
+        st, h = _pfb_create(N, 2, np.zeros(1), mode=mode)
+        assert st == rf.RF_EUNSUPPORTED
 
 
 def test_pfb_create_rejects_bad_arguments():
