@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "pfb", "ddc", "tx", "precision", "serving", "copyprobe"])
+                    choices=["all", "pfb", "ddc", "tx", "large", "precision", "serving", "copyprobe"])
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -351,6 +351,50 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     }, (w, d)
 
 
+# ------------------------------------------------------------- large N
+
+def bench_large(rf, torch, siggen, steps, warmup):
+    """N = 10^5 channels (Sec. III.A, Fig. 3), M = 8, Kaiser(9): 2^27 samples of
+    the production stream in 2^24-sample buffers, through the fold pass and
+    the four-step FFT (N = 250 x 400)."""
+    w = siggen.pfb_production()
+    N, M = 100000, 8
+    h = siggen.pfb_prototype(N, M, "kaiser", 9.0)
+    nsamp = 1 << 27
+    buf = 1 << 24
+    d = siggen.iq_torch(w.stream, 0, nsamp)
+    nbuf = nsamp // buf
+    p = rf.Pfb(N, M, h, max_samples_per_call=buf)
+    fmax = buf // N + 2
+    out = torch.empty((nbuf, fmax, N), dtype=torch.complex64, device="cuda")
+    s = torch.cuda.current_stream()
+    sh = s.cuda_stream
+
+    def step():
+        for b in range(nbuf):
+            p.process_ptr(d.data_ptr() + 4 * b * buf, buf, out.data_ptr() + 8 * b * fmax * N, fmax, sh)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kern_s = ms / 1e3 / (steps * nbuf)
+    p.close()
+    # device traffic of the three passes: fold 4 B in + 8 B out, two FFT
+    # steps 16 B each per sample (12 B/sample is the method's minimum)
+    return {"value": steps * nsamp / (ms / 1e3) / 1e6, "unit": "Msamples/s",
+            "us_per_buffer": kern_s * 1e6,
+            "hbm_gbs_44B_per_sample": 44.0 * buf / kern_s / 1e9,
+            "config": {"workload": "pfb N=100000 M=8 kaiser9, 2^27 samples in 2^24-sample buffers, "
+                                   "fold + four-step FFT (250 x 400)", "N": N, "M": M}}
+
+
 # -------------------------------------------------------------------- Tx
 
 def bench_tx(rf, torch, siggen, steps, warmup):
@@ -571,6 +615,12 @@ def main():
             rec["config"] = r["config"]
             rec["roofline"] = r["roofline"]
         log("ddc: %.0f Msamples/s, %.1f us/launch" % (r["value"], r["kernel_us"]))
+    if a.workload in ("all", "large"):
+        rec["large_n"] = bench_large(rf, torch, siggen, max(1, min(a.steps, 5)), 1)
+        log("large N=10^5: %.0f Msamples/s" % rec["large_n"]["value"])
+        if rec["value"] is None:
+            rec["value"] = rec["large_n"]["value"]
+            rec["config"] = rec["large_n"]["config"]
     if a.workload in ("all", "tx"):
         r, keep["tx"] = bench_tx(rf, torch, siggen, a.steps, a.warmup)
         rec["tx"] = r

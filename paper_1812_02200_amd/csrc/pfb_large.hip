@@ -68,31 +68,45 @@ __device__ __forceinline__ void dft_r(cf *v)
 constexpr int kFoldWG = 256;
 constexpr int kFoldFrames = 32;   // frames per thread
 
+template <int M>
 __global__ void __launch_bounds__(kFoldWG) large_fold(PfbLaunch a, cf *v)
 {
     const int64_t N = a.N;
-    const int M = a.M;
     const int64_t n = (int64_t)blockIdx.x * kFoldWG + threadIdx.x;
     const int64_t p0 = (int64_t)blockIdx.y * kFoldFrames;
     const VStream vs = a.vs;
+    auto ld = [&](int64_t vi) __attribute__((always_inline)) {
+        const uint32_t w = vi < vs.H ? vs.hist[vi] : vs.in[vi - vs.H];
+        return cf{(float)(int16_t)(w & 0xffffu), (float)(int16_t)(w >> 16)};
+    };
     if (n < N) {
-        float h[16];
+        float h[M];
+        cf xw[M];   // window: slot (b - p0) mod M holds block b
 #pragma unroll
-        for (int m = 0; m < 16; ++m) h[m] = m < M ? a.taps[m * N + n] : 0.f;
+        for (int m = 0; m < M; ++m) h[m] = a.taps[m * N + n];
         const int64_t p1 = min(p0 + kFoldFrames, a.F);
-        for (int64_t p = p0; p < p1; ++p) {
-            cf s = {0.f, 0.f};
+        if (p0 < p1) {
 #pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                if (m < M) {
-                    const int64_t vi = (p + m) * N + n;
-                    const uint32_t w = vi < vs.H ? vs.hist[vi] : vs.in[vi - vs.H];
-                    const float xr = (float)(int16_t)(w & 0xffffu), xi = (float)(int16_t)(w >> 16);
-                    s.x = __builtin_fmaf(h[m], xr, s.x);
-                    s.y = __builtin_fmaf(h[m], xi, s.y);
+            for (int m = 0; m < M - 1; ++m) xw[m] = ld((p0 + m) * N + n);
+        }
+        // frames in groups of M so that every window index is a constant
+        for (int64_t pb = p0; pb < p1; pb += M) {
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const int64_t p = pb + q;
+                if (p < p1) {
+                    // block p + M - 1 enters the window, in the slot block p - 1 left
+                    xw[(q + M - 1) % M] = ld((p + M - 1) * N + n);
+                    cf s = {0.f, 0.f};
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        const cf x = xw[(q + m) % M];
+                        s.x = __builtin_fmaf(h[m], x.x, s.x);
+                        s.y = __builtin_fmaf(h[m], x.y, s.y);
+                    }
+                    v[p * N + n] = s;
                 }
             }
-            v[p * N + n] = s;
         }
     }
     // retained history for the next call, spread over the whole grid
@@ -106,18 +120,24 @@ __global__ void __launch_bounds__(kFoldWG) large_fold(PfbLaunch a, cf *v)
 
 // --------------------------------------------------------- batched LDS FFT
 
-constexpr int kStepWG = 256;
+constexpr int kStepWG = 512;
 
 // One radix-R Stockham pass over TB transforms of length L (row stride Lp)
 // from A to B: butterfly j of span ns reads A[j + r L/R], applies
 // W_{ns R}^{k r} (k = j mod ns, = W_L^{k r tstride}) and writes B[(j/ns) ns R + k + r ns].
+// a / b for 0 <= a < 2^20, 1 <= b <= 2^13 through the float reciprocal: the
+// quotient (a + 1/2) / b is at least 1/(2b) away from an integer, far more
+// than the rounding error, so truncation gives floor(a / b) exactly.
+__device__ __forceinline__ int qdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
+
 template <int R>
 __device__ __forceinline__ void stock_pass(const cf *A, cf *B, int Lp, int TB, int nb, int ns, int tstride,
-                                           const cf *__restrict__ tw, int tid)
+                                           const cf *tw, int tid)
 {
+    const float inv_nb = 1.0f / (float)nb, inv_ns = 1.0f / (float)ns;
     for (int idx = tid; idx < TB * nb; idx += kStepWG) {
-        const int t = idx / nb, j = idx - t * nb;
-        const int k = j % ns;
+        const int t = qdiv(idx, inv_nb), j = idx - t * nb;
+        const int q = qdiv(j, inv_ns), k = j - q * ns;
         cf v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = A[t * Lp + j + r * nb];
@@ -126,7 +146,7 @@ __device__ __forceinline__ void stock_pass(const cf *A, cf *B, int Lp, int TB, i
             for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tstride]);
         }
         dft_r<R>(v);
-        const int o = (j / ns) * ns * R + k;
+        const int o = q * ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) B[t * Lp + o + r * ns] = v[r];
     }
@@ -140,21 +160,45 @@ __global__ void __launch_bounds__(kStepWG) large_fft_step(StepDesc d, int64_t N,
     extern __shared__ cf sm[];
     const int L = d.L, TB = d.TB, Lp = L + 1;   // odd row stride: columns spread over banks
     cf *A = sm, *B = sm + (size_t)TB * Lp;
+    cf *twl = B + (size_t)TB * Lp;             // W_L^j staged in LDS
     const int tid = threadIdx.x;
+    __shared__ int64_t bin[16], bout[16], cidx[16];   // per transform: bases and column
+    for (int j = tid; j < L; j += kStepWG) twl[j] = d.tw[j];
     const int64_t T0 = (int64_t)blockIdx.x * TB;
+    if (tid < TB) {
+        const int64_t T = T0 + tid;
+        const int64_t f = T / d.C, c = T - f * d.C;
+        bin[tid] = T < total ? f * N + c * d.in_cs : -1;
+        bout[tid] = T < total ? f * N + c * d.out_cs : -1;
+        cidx[tid] = c;
+    }
+    __syncthreads();
     const int nload = TB * L;
-    // load
-    for (int idx = tid; idx < nload; idx += kStepWG) {
-        int t, i;
-        if (d.in_es == 1) { t = idx / L; i = idx - t * L; }
-        else { i = idx / TB; t = idx - i * TB; }
-        const int64_t T = T0 + t;
-        cf x = {0.f, 0.f};
-        if (T < total) {
-            const int64_t f = T / d.C, c = T - f * d.C;
-            x = d.src[f * N + c * d.in_cs + (int64_t)i * d.in_es];
+    const int lgtb = __builtin_ctz(TB);
+    const float inv_l = 1.0f / (float)L;
+    // load (along the contiguous direction: rows, or TB neighbouring columns),
+    // eight independent loads in flight per thread before they land in LDS
+    constexpr int U = 8;
+    for (int base = 0; base < nload; base += U * kStepWG) {
+        cf x[U];
+        int slot[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * kStepWG + tid;
+            slot[u] = -1;
+            x[u] = cf{0.f, 0.f};
+            if (idx < nload) {
+                int t, i;
+                if (d.in_es == 1) { t = qdiv(idx, inv_l); i = idx - t * L; }
+                else { i = idx >> lgtb; t = idx & (TB - 1); }
+                const int64_t b = bin[t];
+                if (b >= 0) x[u] = d.src[b + (int64_t)i * d.in_es];
+                slot[u] = t * Lp + i;
+            }
         }
-        A[t * Lp + i] = x;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (slot[u] >= 0) A[slot[u]] = x[u];
     }
     __syncthreads();
     // Stockham passes
@@ -164,11 +208,11 @@ __global__ void __launch_bounds__(kStepWG) large_fft_step(StepDesc d, int64_t N,
         const int nb = L / R;
         const int tstride = L / (ns * R);     // W_{ns R}^{e} = W_L^{e * L/(ns R)}
         switch (R) {
-        case 2: stock_pass<2>(A, B, Lp, TB, nb, ns, tstride, d.tw, tid); break;
-        case 3: stock_pass<3>(A, B, Lp, TB, nb, ns, tstride, d.tw, tid); break;
-        case 4: stock_pass<4>(A, B, Lp, TB, nb, ns, tstride, d.tw, tid); break;
-        case 5: stock_pass<5>(A, B, Lp, TB, nb, ns, tstride, d.tw, tid); break;
-        default: stock_pass<8>(A, B, Lp, TB, nb, ns, tstride, d.tw, tid); break;
+        case 2: stock_pass<2>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+        case 3: stock_pass<3>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+        case 4: stock_pass<4>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+        case 5: stock_pass<5>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+        default: stock_pass<8>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
         }
         __syncthreads();
         cf *tmp = A;
@@ -177,19 +221,34 @@ __global__ void __launch_bounds__(kStepWG) large_fft_step(StepDesc d, int64_t N,
         ns *= R;
     }
     // store (with the four-step twiddle W_N^{c k} when asked)
-    for (int idx = tid; idx < nload; idx += kStepWG) {
-        int t, k;
-        if (d.out_es == 1) { t = idx / L; k = idx - t * L; }
-        else { k = idx / TB; t = idx - k * TB; }
-        const int64_t T = T0 + t;
-        if (T >= total) continue;
-        const int64_t f = T / d.C, c = T - f * d.C;
-        cf x = A[t * Lp + k];
-        if (d.thi) {
-            const int64_t e = c * k;          // < N
-            x = cmul(x, cmul(d.thi[e >> d.tsh], d.tlo[e & ((1ll << d.tsh) - 1)]));
+    for (int base = 0; base < nload; base += U * kStepWG) {
+        cf x[U], w1[U], w2[U];
+        int64_t dst[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * kStepWG + tid;
+            dst[u] = -1;
+            if (idx < nload) {
+                int t, k;
+                if (d.out_es == 1) { t = qdiv(idx, inv_l); k = idx - t * L; }
+                else { k = idx >> lgtb; t = idx & (TB - 1); }
+                const int64_t b = bout[t];
+                if (b >= 0) {
+                    dst[u] = b + (int64_t)k * d.out_es;
+                    x[u] = A[t * Lp + k];
+                    if (d.thi) {
+                        const int64_t e = cidx[t] * k;    // < N
+                        w1[u] = d.thi[e >> d.tsh];
+                        w2[u] = d.tlo[e & ((1ll << d.tsh) - 1)];
+                    }
+                }
+            }
         }
-        d.dst[f * N + c * d.out_cs + (int64_t)k * d.out_es] = x;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (dst[u] < 0) continue;
+            d.dst[dst[u]] = d.thi ? cmul(x[u], cmul(w1[u], w2[u])) : x[u];
+        }
     }
 }
 
@@ -224,9 +283,11 @@ bool large_plan(int64_t N, LargePlan *pl)
     if (N <= 4096) {
         n1 = N;
     } else {
-        // the largest divisor <= 4096 whose cofactor is <= 4096 as well
-        for (int64_t d = 4096; d >= 2; --d)
-            if (N % d == 0 && N / d <= 4096) { n1 = d; break; }
+        // the most balanced split N1 * N2 (N1 <= N2 <= 4096): the column step,
+        // whose loads and stores are strided, gets the shorter transforms and
+        // so the most columns per work-group
+        for (int64_t d = 2; d * d <= N; ++d)
+            if (N % d == 0 && N / d <= 4096) n1 = d;
         if (!n1) return false;
         n2 = N / n1;
     }
@@ -278,11 +339,19 @@ void large_table_fill(const LargePlan &pl, float *t)
     }
 }
 
+// transforms per work-group, a power of two <= 16: two batches of TB*(L+1)
+// points plus the L twiddles within 80 KiB of LDS (two work-groups per CU),
+// or within 160 KiB when that would leave fewer than 4 columns per group
 static int step_tb(int L)
 {
-    int tb = 8192 / L;
-    if (tb > 16) tb = 16;
-    return tb < 1 ? 1 : tb;
+    auto fit = [&](int bytes) {
+        int tb = (bytes / 8 - L) / (2 * (L + 1));
+        int p = 1;
+        while (p * 2 <= tb && p * 2 <= 16) p *= 2;
+        return tb < 1 ? 1 : p;
+    };
+    const int a = fit(80 * 1024);
+    return a >= 4 ? a : fit(160 * 1024);
 }
 
 static hipError_t launch_step(const StepDesc &d, int64_t N, int64_t total, hipStream_t s)
@@ -290,7 +359,7 @@ static hipError_t launch_step(const StepDesc &d, int64_t N, int64_t total, hipSt
     if (total <= 0) return hipSuccess;
     const int64_t grid = (total + d.TB - 1) / d.TB;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = 2 * (size_t)d.TB * (d.L + 1) * sizeof(cf);
+    const size_t lds = (2 * (size_t)d.TB * (d.L + 1) + (size_t)d.L) * sizeof(cf);
     hipLaunchKernelGGL(large_fft_step, dim3((unsigned)grid), dim3(kStepWG), lds, s, d, N, total);
     return hipGetLastError();
 }
@@ -303,7 +372,15 @@ hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const Large
     int64_t gy = (a.F + kFoldFrames - 1) / kFoldFrames;
     if (gy < 1) gy = 1;
     if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(large_fold, dim3((unsigned)gx, (unsigned)gy), dim3(kFoldWG), 0, s, a, b.v);
+    switch (a.M) {
+#define RF_FOLD_CASE(m) \
+    case m: hipLaunchKernelGGL(large_fold<m>, dim3((unsigned)gx, (unsigned)gy), dim3(kFoldWG), 0, s, a, b.v); break;
+        RF_FOLD_CASE(1) RF_FOLD_CASE(2) RF_FOLD_CASE(3) RF_FOLD_CASE(4) RF_FOLD_CASE(5) RF_FOLD_CASE(6)
+        RF_FOLD_CASE(7) RF_FOLD_CASE(8) RF_FOLD_CASE(9) RF_FOLD_CASE(10) RF_FOLD_CASE(11) RF_FOLD_CASE(12)
+        RF_FOLD_CASE(13) RF_FOLD_CASE(14) RF_FOLD_CASE(15) RF_FOLD_CASE(16)
+#undef RF_FOLD_CASE
+    default: return hipErrorInvalidValue;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.F == 0) return e;
     const cf *t1 = reinterpret_cast<const cf *>(b.tables);
