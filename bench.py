@@ -52,6 +52,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget per oracle baseline sample")
+    ap.add_argument("--pfb-shape", default=None, metavar="RUN_LEN:VARIANT",
+                    help="use this PFB launch shape instead of autotuning (to profile the shape a "
+                         "timed run chose)")
+    ap.add_argument("--ddc-grid", type=int, default=None,
+                    help="use this DDC grid instead of autotuning")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run of this script (the "
+                         "library's kernels) as markdown, and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_FETCH_DIR",
                                                        "PROBE_WRITE_DIR"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script "
@@ -89,6 +97,8 @@ def profiled_traffic(kernel):
     return None
 
 
+SHAPES = {}                    # launch shapes given on the command line (no autotuning)
+
 COPY_PROBE_ELEMS = 1 << 26     # int32 elements per probe copy: 256 MiB read, 256 MiB written
 
 
@@ -120,6 +130,20 @@ def _per_dispatch(rows, match):
             out.setdefault((r["Kernel_Name"].split("(")[0], int(r["Grid_Size"])), []).append(
                 float(r["Counter_Value"]))
     return out
+
+
+def trace_summary(d):
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+        with open(f) as fh:
+            rows += [r for r in csv.DictReader(fh) if "rfk::" in r["Name"]]
+    print("| kernel | calls | average us | min us | max us | share of GPU time |")
+    print("|---|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"].replace("void ", "").split("(")[0]
+        print("| `%s` | %s | %.1f | %.1f | %.1f | %s%% |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, r["Percentage"]))
 
 
 def pmc_summary(fetch_dir, write_dir, pf_dir, pw_dir):
@@ -177,9 +201,17 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
     nbuf = w.nsamples // w.buffer
     fpb = w.buffer // w.N                           # frames per buffer in steady state
     out = torch.empty((nbuf, fpb, w.N), dtype=torch.complex64, device="cuda")
+    if SHAPES.get("pfb"):
+        os.environ["RFCHAN_PFB_RUN_LEN"], os.environ["RFCHAN_PFB_VARIANT"] = SHAPES["pfb"].split(":")
     p = rf.Pfb(w.N, w.M, w.h, max_samples_per_call=w.buffer)
-    tuned = p.tune(w.buffer)          # launch shape chosen by the autotuner (setup, untimed)
-    log("pfb tuned: %.1f us/launch, run_len=%d variant=%d" % tuned)
+    os.environ.pop("RFCHAN_PFB_RUN_LEN", None)     # this handle only
+    os.environ.pop("RFCHAN_PFB_VARIANT", None)
+    if SHAPES.get("pfb"):
+        rl, var = p.tuned_config()
+        tuned = (float("nan"), rl, var)
+    else:
+        tuned = p.tune(w.buffer)      # launch shape chosen by the autotuner (setup, untimed)
+    log("pfb shape: %.1f us/launch (tuner), run_len=%d variant=%d" % tuned)
     s = torch.cuda.current_stream()
     sh = s.cuda_stream
     base_in, base_out = d.data_ptr(), out.data_ptr()
@@ -273,8 +305,11 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
     nbuf = w.nsamples // w.buffer
     ld = w.buffer // w.D + 2
     out = torch.empty((nbuf, w.words.size, ld), dtype=torch.complex64, device="cuda")
+    if SHAPES.get("ddc"):
+        os.environ["RFCHAN_DDC_GRID"] = str(SHAPES["ddc"])
     dd = rf.Ddc(w.words, w.h, w.D, w.phase0, max_samples_per_call=w.buffer)
-    dtuned = dd.tune(w.buffer)
+    os.environ.pop("RFCHAN_DDC_GRID", None)        # this handle only
+    dtuned = (float("nan"), dd.tuned_config()) if SHAPES.get("ddc") else dd.tune(w.buffer)
     log("ddc tuned: %.1f us/launch, grid=%d" % dtuned)
     s = torch.cuda.current_stream()
     sh = s.cuda_stream
@@ -580,6 +615,13 @@ def main():
     if a.pmc_summary:
         pmc_summary(*a.pmc_summary)
         return
+    if a.trace_summary:
+        trace_summary(a.trace_summary)
+        return
+    if a.pfb_shape:
+        SHAPES["pfb"] = a.pfb_shape
+    if a.ddc_grid:
+        SHAPES["ddc"] = a.ddc_grid
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported" % a.gpus}))
         sys.exit(2)

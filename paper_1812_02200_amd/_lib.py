@@ -235,9 +235,14 @@ class Pfb:
         (microseconds per launch, run_len, variant)."""
         us = ctypes.c_double(0)
         check(lib().pfb_tune(self._h, int(nsamples), _stream_handle(stream), ctypes.byref(us)), "pfb_tune")
+        rl, var = self.tuned_config()
+        return us.value, rl, var
+
+    def tuned_config(self):
+        """(run_len, variant) the next launches use (0: the built-in heuristic)."""
         rl, var = _I32(), _I32()
         check(lib().pfb_tuned_config(self._h, ctypes.byref(rl), ctypes.byref(var)), "pfb_tuned_config")
-        return us.value, rl.value, var.value
+        return rl.value, var.value
 
     def apply_tuned(self, nsamples: int) -> bool:
         st = lib().pfb_apply_tuned(self._h, int(nsamples))
@@ -339,9 +344,13 @@ class Ddc:
         """Autotune the persistent grid for buffers of `nsamples`; returns (us, grid)."""
         us = ctypes.c_double(0)
         check(lib().ddc_tune(self._h, int(nsamples), _stream_handle(stream), ctypes.byref(us)), "ddc_tune")
+        return us.value, self.tuned_config()
+
+    def tuned_config(self) -> int:
+        """The persistent grid the next launches use (0: the built-in default)."""
         g = _I32()
         check(lib().ddc_tuned_config(self._h, ctypes.byref(g)), "ddc_tuned_config")
-        return us.value, g.value
+        return g.value
 
     def apply_tuned(self, nsamples: int) -> bool:
         st = lib().ddc_apply_tuned(self._h, int(nsamples))
