@@ -73,13 +73,14 @@ __global__ void __launch_bounds__(kFoldWG) large_fold(PfbLaunch a, cf *v)
 {
     const int64_t N = a.N;
     const int64_t n = (int64_t)blockIdx.x * kFoldWG + threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.y * kFoldFrames;
     const VStream vs = a.vs;
     auto ld = [&](int64_t vi) __attribute__((always_inline)) {
         const uint32_t w = vi < vs.H ? vs.hist[vi] : vs.in[vi - vs.H];
         return cf{(float)(int16_t)(w & 0xffffu), (float)(int16_t)(w >> 16)};
     };
-    if (n < N) {
+    // frame chunks of kFoldFrames, strided over the grid's y dimension
+    for (int64_t p0 = (int64_t)blockIdx.y * kFoldFrames; n < N && p0 < a.F;
+         p0 += (int64_t)gridDim.y * kFoldFrames) {
         float h[M];
         cf xw[M];   // window: slot (b - p0) mod M holds block b
 #pragma unroll
@@ -371,7 +372,8 @@ hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const Large
     const int64_t gx = (N + kFoldWG - 1) / kFoldWG;
     int64_t gy = (a.F + kFoldFrames - 1) / kFoldFrames;
     if (gy < 1) gy = 1;
-    if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidValue;
+    if (gy > 65535) gy = 65535;        // the kernel strides over further chunks
+    if (gx > 0x7fffffff) return hipErrorInvalidValue;
     switch (a.M) {
 #define RF_FOLD_CASE(m) \
     case m: hipLaunchKernelGGL(large_fold<m>, dim3((unsigned)gx, (unsigned)gy), dim3(kFoldWG), 0, s, a, b.v); break;

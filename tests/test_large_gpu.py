@@ -99,3 +99,23 @@ def test_ten_million_channels_sampled():
     bins = np.unique(np.random.default_rng(1).integers(0, N, 24))
     ref = oracle.pfb_channels(f32(h), N, M, bins, iq=iq)
     assert err_fs(y[:, bins], ref, h.sum()) <= 1e-5
+
+
+def test_small_non_power_of_two_with_many_frames():
+    """N = 18: a buffer of 2^26 samples holds ~3.7M frames, more 32-frame
+    chunks than one grid dimension covers (the fold strides over the rest);
+    sampled frames, the last ones included, against the oracle at all bins."""
+    rf = _rf()
+    import torch
+    N, M = 18, 3
+    h = proto(N, M)
+    n = 1 << 26
+    w = siggen.pfb_small()
+    d = siggen.iq_torch(w.stream, 0, n)
+    y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, [n], torch)
+    iq = d.cpu().numpy()
+    F = oracle.pfb_nframes(n, N, M)
+    assert y.shape == (F, N)
+    frames = np.concatenate([np.arange(64), np.arange(F - 64, F), np.random.default_rng(3).integers(0, F, 128)])
+    ref = oracle.pfb(f32(h), N, M, iq=iq, frames=frames)
+    assert err_fs(y[frames], ref, h.sum()) <= 1e-5
