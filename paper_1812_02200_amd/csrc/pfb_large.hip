@@ -16,7 +16,9 @@
 //     contiguous runs in HBM.  N <= 4096 that is not a power of two is one
 //     step (N1 = N, N2 = 1).
 // Twiddles are FP32 values of FP64 angles: W_L^j tables per transform length
-// and, for W_N^e, the product of two tables W_N^{(e >> s) 2^s} W_N^{e mod 2^s}.
+// and, for W_N^e (e < N <= 2^24), the product of three 256-entry tables
+// W_N^{(e >> 16) 2^16} W_N^{((e >> 8) mod 256) 2^8} W_N^{e mod 256}, small
+// enough to live in LDS beside the transforms.
 #include <math.h>
 #include <stdlib.h>
 
@@ -153,103 +155,158 @@ __device__ __forceinline__ void stock_pass(const cf *A, cf *B, int Lp, int TB, i
     }
 }
 
+// Buffer resources over a tile's two frames: accesses at offsets at or beyond
+// the range are not made (loads return zero, stores are dropped), so every
+// load and store below is issued unconditionally and the number of memory
+// operations between a load and its use is fixed at compile time.
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));   // (whole-vector bit casts only)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const cf *p, uint32_t bytes)
+{
+    // the values are uniform; readfirstlane puts them in scalar registers
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const uint32_t n = __builtin_amdgcn_readfirstlane(bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(((uint64_t)hi << 32) | lo), (short)0,
+                                             (int)n, 0x00020000);
+}
+constexpr int kOff = 1 << 30;   // an offset outside every range
+
 // Transform T = f*C + c (frame f, transform c of the frame) reads element i at
 // src[f*N + c*in_cs + i*in_es] and writes bin k at dst[f*N + c*out_cs + k*out_es];
-// a work-group takes TB consecutive transforms.
-__global__ void __launch_bounds__(kStepWG) large_fft_step(StepDesc d, int64_t N, int64_t total)
+// tile b is the TB consecutive transforms from b*TB.  The
+// grid is persistent: a work-group walks tiles b, b + G, ...; the loads of its
+// next tile are issued before the passes of the current one and land in LDS
+// only after its stores have been issued (U per thread, TB*L <= U*kStepWG), so
+// a tile's loads and stores overlap the neighbouring tiles' work.
+template <int U>
+__global__ void __launch_bounds__(kStepWG) large_fft_step(StepDesc d, int64_t N, int64_t total, int64_t ntiles)
 {
     extern __shared__ cf sm[];
     const int L = d.L, TB = d.TB, Lp = L + 1;   // odd row stride: columns spread over banks
-    cf *A = sm, *B = sm + (size_t)TB * Lp;
-    cf *twl = B + (size_t)TB * Lp;             // W_L^j staged in LDS
+    cf *const A0 = sm, *const B0 = sm + (size_t)TB * Lp;
+    cf *twl = B0 + (size_t)TB * Lp;            // W_L^j staged in LDS
+    cf *t3l = twl + L;                         // the four-step tables, when used
     const int tid = threadIdx.x;
-    __shared__ int64_t bin[16], bout[16], cidx[16];   // per transform: bases and column
+    // per transform of a tile: input and output offsets (elements, from the
+    // tile's first frame) and column; two sets, for the tile being stored and
+    // the tile being loaded
+    __shared__ int32_t bin[2][16], bout[2][16], cidx[2][16];
     for (int j = tid; j < L; j += kStepWG) twl[j] = d.tw[j];
-    const int64_t T0 = (int64_t)blockIdx.x * TB;
-    if (tid < TB) {
-        const int64_t T = T0 + tid;
-        const int64_t f = T / d.C, c = T - f * d.C;
-        bin[tid] = T < total ? f * N + c * d.in_cs : -1;
-        bout[tid] = T < total ? f * N + c * d.out_cs : -1;
-        cidx[tid] = c;
-    }
-    __syncthreads();
+    if (d.t3)
+        for (int j = tid; j < 768; j += kStepWG) t3l[j] = d.t3[j];
     const int nload = TB * L;
     const int lgtb = __builtin_ctz(TB);
     const float inv_l = 1.0f / (float)L;
-    // load (along the contiguous direction: rows, or TB neighbouring columns),
-    // eight independent loads in flight per thread before they land in LDS
-    constexpr int U = 8;
-    for (int base = 0; base < nload; base += U * kStepWG) {
-        cf x[U];
-        int slot[U];
+    // a tile's transforms lie in at most TB/C + 2 frames; below 2^30 bytes for
+    // every supported N (N <= 2^24 with C >= TB, or N <= 4096 C)
+    const uint32_t span = (uint32_t)((TB / d.C + 2) * N * (int64_t)sizeof(cf));
+    auto frame0 = [&](int64_t tile) __attribute__((always_inline)) { return tile * TB / d.C; };
+    auto bases = [&](int64_t tile, int s) __attribute__((always_inline)) {
+        if (tid < TB) {
+            const int64_t T = tile * TB + tid;
+            const int64_t f = T / d.C, c = T - f * d.C;
+            const int64_t rel = (f - frame0(tile)) * N;
+            bin[s][tid] = T < total ? (int32_t)(rel + c * d.in_cs) : -1;
+            bout[s][tid] = T < total ? (int32_t)(rel + c * d.out_cs) : -1;
+            cidx[s][tid] = (int32_t)c;
+        }
+    };
+    // element u of this thread: idx = u*kStepWG + tid, along the contiguous
+    // direction (rows, or TB neighbouring columns)
+    auto slot_of = [&](int idx, int &t, int &i) __attribute__((always_inline)) {
+        if (d.in_es == 1) { t = qdiv(idx, inv_l); i = idx - t * L; }
+        else { i = idx >> lgtb; t = idx & (TB - 1); }
+    };
+    cf x[U];
+    auto load = [&](int64_t tile, int s) __attribute__((always_inline)) {
+        const __amdgpu_buffer_rsrc_t r =
+            tile_rsrc(d.src + frame0(tile) * N, tile < ntiles ? span : 0u);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = base + u * kStepWG + tid;
-            slot[u] = -1;
-            x[u] = cf{0.f, 0.f};
+            const int idx = u * kStepWG + tid;
+            int t = 0, i = 0, off = kOff;
+            if (idx < nload) {
+                slot_of(idx, t, i);
+                const int b = bin[s][t];
+                if (b >= 0) off = (b + i * (int)d.in_es) * (int)sizeof(cf);
+            }
+            const v2f w = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+            x[u] = cf{w.x, w.y};
+        }
+    };
+    auto put = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = u * kStepWG + tid;
             if (idx < nload) {
                 int t, i;
-                if (d.in_es == 1) { t = qdiv(idx, inv_l); i = idx - t * L; }
-                else { i = idx >> lgtb; t = idx & (TB - 1); }
-                const int64_t b = bin[t];
-                if (b >= 0) x[u] = d.src[b + (int64_t)i * d.in_es];
-                slot[u] = t * Lp + i;
+                slot_of(idx, t, i);
+                A0[t * Lp + i] = x[u];
             }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (slot[u] >= 0) A[slot[u]] = x[u];
-    }
-    __syncthreads();
-    // Stockham passes
-    int ns = 1;
-    for (int ps = 0; ps < d.nr; ++ps) {
-        const int R = d.rad[ps];
-        const int nb = L / R;
-        const int tstride = L / (ns * R);     // W_{ns R}^{e} = W_L^{e * L/(ns R)}
-        switch (R) {
-        case 2: stock_pass<2>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
-        case 3: stock_pass<3>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
-        case 4: stock_pass<4>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
-        case 5: stock_pass<5>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
-        default: stock_pass<8>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+    };
+
+    int64_t tile = blockIdx.x;
+    bases(tile, 0);
+    __syncthreads();   // twiddles and the first bases
+    load(tile, 0);
+    put();
+    for (int s = 0; tile < ntiles; tile += gridDim.x, s ^= 1) {
+        const int64_t nxt = tile + gridDim.x;
+        if (nxt < ntiles) bases(nxt, s ^ 1);
+        __syncthreads();   // this tile in LDS, the next tile's bases visible
+        load(nxt, s ^ 1);  // a zero-range resource past the last tile: no access
+        // Stockham passes
+        cf *A = A0, *B = B0;
+        int ns = 1;
+        for (int ps = 0; ps < d.nr; ++ps) {
+            const int R = d.rad[ps];
+            const int nb = L / R;
+            const int tstride = L / (ns * R);     // W_{ns R}^{e} = W_L^{e * L/(ns R)}
+            switch (R) {
+            case 2: stock_pass<2>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+            case 3: stock_pass<3>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+            case 4: stock_pass<4>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+            case 5: stock_pass<5>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+            default: stock_pass<8>(A, B, Lp, TB, nb, ns, tstride, twl, tid); break;
+            }
+            __syncthreads();
+            cf *tmp = A;
+            A = B;
+            B = tmp;
+            ns *= R;
         }
-        __syncthreads();
-        cf *tmp = A;
-        A = B;
-        B = tmp;
-        ns *= R;
-    }
-    // store (with the four-step twiddle W_N^{c k} when asked)
-    for (int base = 0; base < nload; base += U * kStepWG) {
-        cf x[U], w1[U], w2[U];
-        int64_t dst[U];
+        // store (with the four-step twiddle W_N^{c k} when asked)
+        const __amdgpu_buffer_rsrc_t w = tile_rsrc(d.dst + frame0(tile) * N, span);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = base + u * kStepWG + tid;
-            dst[u] = -1;
+            const int idx = u * kStepWG + tid;
+            int off = kOff;
+            cf y = {0.f, 0.f};
             if (idx < nload) {
                 int t, k;
                 if (d.out_es == 1) { t = qdiv(idx, inv_l); k = idx - t * L; }
                 else { k = idx >> lgtb; t = idx & (TB - 1); }
-                const int64_t b = bout[t];
+                const int b = bout[s][t];
                 if (b >= 0) {
-                    dst[u] = b + (int64_t)k * d.out_es;
-                    x[u] = A[t * Lp + k];
-                    if (d.thi) {
-                        const int64_t e = cidx[t] * k;    // < N
-                        w1[u] = d.thi[e >> d.tsh];
-                        w2[u] = d.tlo[e & ((1ll << d.tsh) - 1)];
+                    off = (b + k * (int)d.out_es) * (int)sizeof(cf);
+                    y = A[t * Lp + k];
+                    if (d.t3) {
+                        const int e = cidx[s][t] * k;    // < N <= 2^24
+                        y = cmul(y, cmul(cmul(t3l[512 + (e >> 16)], t3l[256 + ((e >> 8) & 255)]),
+                                         t3l[e & 255]));
                     }
                 }
             }
+            v2f v;
+            v.x = y.x;
+            v.y = y.y;
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), w, off, 0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (dst[u] < 0) continue;
-            d.dst[dst[u]] = d.thi ? cmul(x[u], cmul(w1[u], w2[u])) : x[u];
-        }
+        __syncthreads();   // the tile buffers and this set of bases are free again
+        put();             // the next tile (its loads have had the passes and stores to land)
     }
 }
 
@@ -310,12 +367,9 @@ static void fill_wl(int64_t L, float *tw)   // W_L^j = exp(-2 pi i j / L), j < L
     }
 }
 
-int large_tsh(int64_t N) { return N > 4096 ? 12 : 0; }
-
 size_t large_table_floats(const LargePlan &pl)
 {
-    const int64_t hi = (pl.N >> large_tsh(pl.N)) + 1;
-    return 2 * ((size_t)pl.N1 + (size_t)pl.N2 + (size_t)hi + (1ull << large_tsh(pl.N)));
+    return 2 * ((size_t)pl.N1 + (size_t)pl.N2 + 768);
 }
 
 void large_table_fill(const LargePlan &pl, float *t)
@@ -325,44 +379,62 @@ void large_table_fill(const LargePlan &pl, float *t)
     t += 2 * (size_t)pl.N1;
     fill_wl(pl.N2, t);
     t += 2 * (size_t)pl.N2;
-    const int s = large_tsh(pl.N);
-    const int64_t hi = (pl.N >> s) + 1;
-    for (int64_t j = 0; j < hi; ++j) {      // W_N^{j 2^s}
-        const double a = -two_pi * (double)((j << s) % pl.N) / (double)pl.N;
-        t[2 * j] = (float)cos(a);
-        t[2 * j + 1] = (float)sin(a);
-    }
-    t += 2 * (size_t)hi;
-    for (int64_t j = 0; j < (1ll << s); ++j) {   // W_N^j
-        const double a = -two_pi * (double)j / (double)pl.N;
-        t[2 * j] = (float)cos(a);
-        t[2 * j + 1] = (float)sin(a);
-    }
+    // W_N^{j}, W_N^{256 j}, W_N^{65536 j} for j < 256 (exponents reduced mod N)
+    for (int lvl = 0; lvl < 3; ++lvl)
+        for (int64_t j = 0; j < 256; ++j) {
+            const int64_t e = (j << (8 * lvl)) % pl.N;
+            const double a = -two_pi * (double)e / (double)pl.N;
+            t[2 * (256 * lvl + j)] = (float)cos(a);
+            t[2 * (256 * lvl + j) + 1] = (float)sin(a);
+        }
 }
 
 // transforms per work-group, a power of two <= 16: two batches of TB*(L+1)
-// points plus the L twiddles within 80 KiB of LDS (two work-groups per CU),
-// or within 160 KiB when that would leave fewer than 4 columns per group
-static int step_tb(int L)
+// points plus the L twiddles (and `extra` more values) within 80 KiB of LDS
+// (two work-groups per CU) and at most 8 points per thread, or within 160 KiB
+// and 16 points per thread when that would leave fewer than 4 columns per group
+static int step_tb(int L, int extra)
 {
-    auto fit = [&](int bytes) {
-        int tb = (bytes / 8 - L) / (2 * (L + 1));
+    auto fit = [&](int bytes, int pts) {
+        int tb = (bytes / 8 - L - extra) / (2 * (L + 1));
+        if (tb > pts * kStepWG / L) tb = pts * kStepWG / L;
         int p = 1;
         while (p * 2 <= tb && p * 2 <= 16) p *= 2;
         return tb < 1 ? 1 : p;
     };
-    const int a = fit(80 * 1024);
-    return a >= 4 ? a : fit(160 * 1024);
+    const int a = fit(80 * 1024, 8);
+    return a >= 4 ? a : fit(160 * 1024, 16);
+}
+
+template <int U>
+static hipError_t launch_step_u(const StepDesc &d, int64_t N, int64_t total, hipStream_t s)
+{
+    const int64_t ntiles = (total + d.TB - 1) / d.TB;
+    const size_t lds = (2 * (size_t)d.TB * (d.L + 1) + (size_t)d.L + (d.t3 ? 768 : 0)) * sizeof(cf);
+    // persistent grid: the work-groups that are resident at once
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, large_fft_step<U>, kStepWG, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int64_t grid = ntiles < (int64_t)per_cu * cus ? ntiles : (int64_t)per_cu * cus;
+    hipLaunchKernelGGL(large_fft_step<U>, dim3((unsigned)grid), dim3(kStepWG), lds, s, d, N, total, ntiles);
+    return hipGetLastError();
 }
 
 static hipError_t launch_step(const StepDesc &d, int64_t N, int64_t total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
-    const int64_t grid = (total + d.TB - 1) / d.TB;
-    if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = (2 * (size_t)d.TB * (d.L + 1) + (size_t)d.L) * sizeof(cf);
-    hipLaunchKernelGGL(large_fft_step, dim3((unsigned)grid), dim3(kStepWG), lds, s, d, N, total);
-    return hipGetLastError();
+    const int64_t pts = (int64_t)d.TB * d.L;
+    if (pts <= 8 * kStepWG) return launch_step_u<8>(d, N, total, s);
+    if (pts <= 16 * kStepWG) return launch_step_u<16>(d, N, total, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const LargeBuffers &b, hipStream_t s)
@@ -387,8 +459,7 @@ hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const Large
     if (e != hipSuccess || a.F == 0) return e;
     const cf *t1 = reinterpret_cast<const cf *>(b.tables);
     const cf *t2 = t1 + pl.N1;
-    const cf *thi = t2 + pl.N2;
-    const cf *tlo = thi + ((N >> large_tsh(N)) + 1);
+    const cf *t3 = t2 + pl.N2;
     cf *out = reinterpret_cast<cf *>(a.out);
     StepDesc d{};
     if (pl.N2 == 1) {
@@ -398,7 +469,7 @@ hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const Large
         for (int i = 0; i < d.nr; ++i) d.rad[i] = pl.rad1[i];
         d.tw = t1;
         d.C = 1;
-        d.TB = step_tb(d.L);
+        d.TB = step_tb(d.L, 0);
         d.in_cs = d.out_cs = 0;
         d.in_es = d.out_es = 1;
         d.src = b.v;
@@ -411,14 +482,12 @@ hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const Large
     for (int i = 0; i < d.nr; ++i) d.rad[i] = pl.rad1[i];
     d.tw = t1;
     d.C = pl.N2;
-    d.TB = step_tb(d.L);
+    d.TB = step_tb(d.L, 768);
     d.in_cs = 1;
     d.in_es = pl.N2;
     d.out_cs = 1;
     d.out_es = pl.N2;
-    d.thi = thi;
-    d.tlo = tlo;
-    d.tsh = large_tsh(N);
+    d.t3 = t3;
     d.src = b.v;
     d.dst = b.y;
     e = launch_step(d, N, a.F * pl.N2, s);
@@ -430,7 +499,7 @@ hipError_t launch_pfb_large(const PfbLaunch &a, const LargePlan &pl, const Large
     for (int i = 0; i < d2.nr; ++i) d2.rad[i] = pl.rad2[i];
     d2.tw = t2;
     d2.C = pl.N1;
-    d2.TB = step_tb(d2.L);
+    d2.TB = step_tb(d2.L, 0);
     d2.in_cs = pl.N2;
     d2.in_es = 1;
     d2.out_cs = 1;

@@ -1,6 +1,6 @@
 // Instantiations of the fused PFB kernel for N = 1024 (M = 1..16), all bins or
-// chosen channels. plus the
-// tunable variants of the M = 8 kernel (double-buffered LDS, store type).
+// chosen channels, plus the tunable variants of the M = 8 kernel
+// (double-buffered LDS, store type).
 #include "pfb_kernels.hpp"
 
 namespace rfk {

@@ -118,7 +118,7 @@ struct LargePlan {
 struct LargeBuffers {
     cf *v = nullptr;         // folded frames [frames x N]
     cf *y = nullptr;         // first-step output [frames x N]
-    const float *tables = nullptr;   // W_N1^j, W_N2^j, then the two W_N tables
+    const float *tables = nullptr;   // W_N1^j, W_N2^j, then the three W_N tables
 };
 struct StepDesc {
     int L, nr, TB;
@@ -126,8 +126,8 @@ struct StepDesc {
     const cf *tw;            // W_L^j
     int64_t C;               // transforms per frame
     int64_t in_cs, in_es, out_cs, out_es;
-    const cf *thi, *tlo;     // four-step twiddle W_N^e = thi[e >> tsh] * tlo[e mod 2^tsh], or null
-    int tsh;
+    const cf *t3;            // four-step twiddle tables (3 x 256, staged in LDS), or null:
+                             // W_N^e = t3[512 + (e >> 16)] * t3[256 + ((e >> 8) & 255)] * t3[e & 255]
     const cf *src;
     cf *dst;
 };
