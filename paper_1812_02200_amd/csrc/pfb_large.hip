@@ -3,9 +3,10 @@
 // The paper's bank also runs with N = 10^5 (Sec. III.A, Fig. 3) and mentions
 // far larger spectra.  There a frame no longer fits one work-group, so the
 // two stages run as separate passes over HBM:
-//  1. fold: v_p[n] = sum_m h[mN+n] x[pN+mN+n], one thread per column walking
-//     a chunk of frames (each input sample is read from HBM once; the M-1
-//     older blocks come back from the cache), written to a scratch array;
+//  1. fold: v_p[n] = sum_m h[mN+n] x[pN+mN+n], one thread per column and
+//     chunk of frames, all of the chunk's input blocks requested at once (each
+//     input sample is read from HBM about once: neighbouring chunks share M-1
+//     blocks), written to a scratch array;
 //  2. the N-point DFT of every frame by the four-step method, N = N1 * N2,
 //     n = N2 n1 + n2, k = k1 + N1 k2:
 //       Y[k1][n2] = W_N^{n2 k1} sum_{n1} v[N2 n1 + n2] W_{N1}^{n1 k1}
@@ -76,39 +77,39 @@ __global__ void __launch_bounds__(kFoldWG) large_fold(PfbLaunch a, cf *v)
     const int64_t N = a.N;
     const int64_t n = (int64_t)blockIdx.x * kFoldWG + threadIdx.x;
     const VStream vs = a.vs;
-    auto ld = [&](int64_t vi) __attribute__((always_inline)) {
-        const uint32_t w = vi < vs.H ? vs.hist[vi] : vs.in[vi - vs.H];
-        return cf{(float)(int16_t)(w & 0xffffu), (float)(int16_t)(w >> 16)};
-    };
-    // frame chunks of kFoldFrames, strided over the grid's y dimension
+    // frame chunks of kFoldFrames, strided over the grid's y dimension; a
+    // chunk's kFoldFrames + M - 1 input blocks are all requested before the
+    // first is used, so each thread has that many loads in flight
+    constexpr int NB = kFoldFrames + M - 1;
     for (int64_t p0 = (int64_t)blockIdx.y * kFoldFrames; n < N && p0 < a.F;
          p0 += (int64_t)gridDim.y * kFoldFrames) {
         float h[M];
-        cf xw[M];   // window: slot (b - p0) mod M holds block b
 #pragma unroll
         for (int m = 0; m < M; ++m) h[m] = a.taps[m * N + n];
         const int64_t p1 = min(p0 + kFoldFrames, a.F);
-        if (p0 < p1) {
+        const int64_t nb = p1 - p0 + M - 1;   // blocks this chunk reads
+        uint32_t raw[NB];
 #pragma unroll
-            for (int m = 0; m < M - 1; ++m) xw[m] = ld((p0 + m) * N + n);
+        for (int i = 0; i < NB; ++i) {
+            raw[i] = 0;
+            if (i < nb) {
+                const int64_t vi = (p0 + i) * N + n;
+                raw[i] = vi < vs.H ? vs.hist[vi] : vs.in[vi - vs.H];
+            }
         }
-        // frames in groups of M so that every window index is a constant
-        for (int64_t pb = p0; pb < p1; pb += M) {
+        cf x[NB];
 #pragma unroll
-            for (int q = 0; q < M; ++q) {
-                const int64_t p = pb + q;
-                if (p < p1) {
-                    // block p + M - 1 enters the window, in the slot block p - 1 left
-                    xw[(q + M - 1) % M] = ld((p + M - 1) * N + n);
-                    cf s = {0.f, 0.f};
+        for (int i = 0; i < NB; ++i) x[i] = cf{(float)(int16_t)(raw[i] & 0xffffu), (float)(int16_t)(raw[i] >> 16)};
 #pragma unroll
-                    for (int m = 0; m < M; ++m) {
-                        const cf x = xw[(q + m) % M];
-                        s.x = __builtin_fmaf(h[m], x.x, s.x);
-                        s.y = __builtin_fmaf(h[m], x.y, s.y);
-                    }
-                    v[p * N + n] = s;
+        for (int q = 0; q < kFoldFrames; ++q) {
+            if (p0 + q < p1) {
+                cf s = {0.f, 0.f};
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    s.x = __builtin_fmaf(h[m], x[q + m].x, s.x);
+                    s.y = __builtin_fmaf(h[m], x[q + m].y, s.y);
                 }
+                v[(p0 + q) * N + n] = s;
             }
         }
     }
