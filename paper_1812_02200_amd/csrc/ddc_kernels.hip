@@ -195,9 +195,9 @@ __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
 // b of G takes the contiguous units [b W / G, (b+1) W / G) of the whole list.
 // The table is the same for every bank and is loaded once per work-group.
 // Grouped banks have linear oscillators (the serving path has no chirps).
-__global__ void __launch_bounds__(kDdcGroupWG) ddc_group(const GroupHeader *hdr, const DdcItem *items)
+template <int WG>
+__global__ void __launch_bounds__(WG) ddc_group(const GroupHeader *hdr, const DdcItem *items)
 {
-    constexpr int WG = kDdcGroupWG;
     __shared__ float2 lds[kDdcLds];
     const int nitems = hdr->count;
     const int64_t total = hdr->total;
@@ -230,16 +230,29 @@ __global__ void __launch_bounds__(kDdcGroupWG) ddc_group(const GroupHeader *hdr,
     }
 }
 
+int ddc_group_wg(int ntones)
+{
+    return ntones <= 64 ? 64 : ntones <= 128 ? 128 : ntones <= 256 ? 256 : ntones <= 512 ? 512 : 1024;
+}
+
 int64_t ddc_group_units(const DdcLaunch &a)
 {
-    const int TC = (a.ntones + kDdcGroupWG - 1) / kDdcGroupWG;
+    const int wg = ddc_group_wg(a.ntones);
+    const int TC = (a.ntones + wg - 1) / wg;
     return (int64_t)TC * a.nout + 1;
 }
 
-hipError_t launch_ddc_group(const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s)
+hipError_t launch_ddc_group(int wg, const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s)
 {
     if (grid < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ddc_group, dim3((unsigned)grid), dim3(kDdcGroupWG), 0, s, hdr, items);
+    switch (wg) {
+    case 64: hipLaunchKernelGGL(ddc_group<64>, dim3((unsigned)grid), dim3(64), 0, s, hdr, items); break;
+    case 128: hipLaunchKernelGGL(ddc_group<128>, dim3((unsigned)grid), dim3(128), 0, s, hdr, items); break;
+    case 256: hipLaunchKernelGGL(ddc_group<256>, dim3((unsigned)grid), dim3(256), 0, s, hdr, items); break;
+    case 512: hipLaunchKernelGGL(ddc_group<512>, dim3((unsigned)grid), dim3(512), 0, s, hdr, items); break;
+    case 1024: hipLaunchKernelGGL(ddc_group<1024>, dim3((unsigned)grid), dim3(1024), 0, s, hdr, items); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -264,11 +277,13 @@ static hipError_t launch_wg(const DdcLaunch &a, hipStream_t s)
 hipError_t launch_ddc(const DdcLaunch &a, hipStream_t s)
 {
     if (a.T < 1 || a.T > 4096 || a.D < 1 || a.ntones < 1) return hipErrorInvalidValue;
-    if (a.ntones <= 64) return launch_wg<64>(a, s);
-    if (a.ntones <= 128) return launch_wg<128>(a, s);
-    if (a.ntones <= 256) return launch_wg<256>(a, s);
-    if (a.ntones <= 512) return launch_wg<512>(a, s);
-    return launch_wg<1024>(a, s);
+    switch (ddc_group_wg(a.ntones)) {
+    case 64: return launch_wg<64>(a, s);
+    case 128: return launch_wg<128>(a, s);
+    case 256: return launch_wg<256>(a, s);
+    case 512: return launch_wg<512>(a, s);
+    default: return launch_wg<1024>(a, s);
+    }
 }
 
 }  // namespace rfk

@@ -95,14 +95,17 @@ int pfb_default_run_len(int N, int M, int64_t F);
 
 hipError_t launch_ddc(const DdcLaunch &a, hipStream_t s);
 
-constexpr int kDdcGroupWG = 256;   // threads (= tones per chunk) of the grouped DDC kernel
 struct DdcItem {
     DdcLaunch a;
     int64_t unit_begin;     // first work unit of this item
 };
+// Threads (= tones per chunk) of the work-group that serves a bank of `ntones`
+// (64 .. 1024, the same rule as the single-stream launch); a grouped launch
+// holds items of one such size only.
+int ddc_group_wg(int ntones);
 // Work units of one item in a grouped launch: (tone chunk, output) pairs + 1 tail.
 int64_t ddc_group_units(const DdcLaunch &a);
-hipError_t launch_ddc_group(const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s);
+hipError_t launch_ddc_group(int wg, const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s);
 int ddc_default_grid(int ntones, int64_t nout);
 
 // Number of float entries of the half-wave sine table.

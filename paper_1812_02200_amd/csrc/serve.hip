@@ -107,8 +107,10 @@ struct rfs_server {
     std::atomic<bool> stop{false};
     Blob blobs[2];
     int next_blob = 0;
-    // class table: distinct (N, M) of open PFB streams -> table index
+    // class tables: distinct (N, M) of open PFB streams -> table index t,
+    // then distinct DDC work-group sizes -> table C + index
     std::vector<std::pair<int, int>> classes;
+    std::vector<int> ddc_classes;
     int class_version = 0;
     size_t region = 0;                 // bytes per table region
     rfs_stats st{};
@@ -127,7 +129,8 @@ size_t region_bytes(int max_items)
     return align_up(sizeof(rfk::GroupHeader), 256) + align_up(item * (size_t)max_items, 256);
 }
 
-// Tables: [PFB class 0] ... [PFB class C-1] [DDC]; C fixed by class_version.
+// Tables: [PFB class 0] ... [PFB class C-1] [DDC class 0] ... [DDC class D-1];
+// C and D fixed by class_version.
 rfk::GroupHeader *hdr_at(void *base, size_t region, int t)
 {
     return reinterpret_cast<rfk::GroupHeader *>((char *)base + region * t);
@@ -173,27 +176,45 @@ int class_index(rfs_server *S, int N, int M)
     return -1;
 }
 
-// Recompute the class list from the open streams (caller holds mu).
+int ddc_class_index(rfs_server *S, int ntones)
+{
+    const int wg = rfk::ddc_group_wg(ntones);
+    for (size_t i = 0; i < S->ddc_classes.size(); ++i)
+        if (S->ddc_classes[i] == wg) return (int)i;
+    return -1;
+}
+
+// Recompute the class lists from the open streams (caller holds mu).  A DDC
+// bank is served by a work-group of its own size (one lane per tone, up to
+// 1024), as in a single-stream launch.
 void rebuild_classes(rfs_server *S)
 {
     std::vector<std::pair<int, int>> c;
-    for (auto &kv : S->streams)
+    std::vector<int> dc;
+    for (auto &kv : S->streams) {
         if (kv.second->kinds & RFS_PFB) {
             std::pair<int, int> k(kv.second->N, kv.second->M);
             if (std::find(c.begin(), c.end(), k) == c.end()) c.push_back(k);
         }
+        if (kv.second->kinds & RFS_DDC) {
+            const int wg = rfk::ddc_group_wg(kv.second->ntones);
+            if (std::find(dc.begin(), dc.end(), wg) == dc.end()) dc.push_back(wg);
+        }
+    }
     std::sort(c.begin(), c.end());
-    if (c != S->classes) {
+    std::sort(dc.begin(), dc.end());
+    if (c != S->classes || dc != S->ddc_classes) {
         S->classes = c;
+        S->ddc_classes = dc;
         ++S->class_version;
     }
 }
 
 int pfb_grid(rfs_server *S, int N) { return N >= 2048 ? S->cus : 2 * S->cus; }
 
-// Capture the batch graph for the current class list into blob b:
-// upload tables, then fork: one grouped kernel per class and the DDC kernel on
-// parallel branches, join.
+// Capture the batch graph for the current class lists into blob b:
+// upload tables, then fork: one grouped kernel per PFB class and per DDC class
+// on parallel branches, join.
 int capture_graph(rfs_server *S, Blob &b)
 {
     if (b.exec) {
@@ -205,11 +226,12 @@ int capture_graph(rfs_server *S, Blob &b)
         b.graph = nullptr;
     }
     const int C = (int)S->classes.size();
+    const int NT = C + (int)S->ddc_classes.size();
     hipError_t e = hipStreamBeginCapture(S->hs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return set_error(RF_EDEVICE, "hipStreamBeginCapture failed");
-    hipError_t err = hipMemcpyAsync(b.dev, b.host, S->region * (C + 1), hipMemcpyHostToDevice, S->hs);
+    hipError_t err = hipMemcpyAsync(b.dev, b.host, S->region * NT, hipMemcpyHostToDevice, S->hs);
     if (err == hipSuccess) err = hipEventRecord(S->fork_ev[0], S->hs);
-    for (int t = 0; t <= C && err == hipSuccess; ++t) {
+    for (int t = 0; t < NT && err == hipSuccess; ++t) {
         hipStream_t bs = S->branch[t % kMaxBranches];
         err = hipStreamWaitEvent(bs, S->fork_ev[0], 0);
         if (err != hipSuccess) break;
@@ -219,9 +241,10 @@ int capture_graph(rfs_server *S, Blob &b)
                                         items_at<rfk::PfbItem>(b.dev, S->region, t),
                                         pfb_grid(S, S->classes[t].first), bs);
         else
-            err = rfk::launch_ddc_group(h, items_at<rfk::DdcItem>(b.dev, S->region, t), S->cus, bs);
+            err = rfk::launch_ddc_group(S->ddc_classes[t - C], h, items_at<rfk::DdcItem>(b.dev, S->region, t),
+                                        S->cus, bs);
     }
-    const int used = std::min(C + 1, kMaxBranches);   // join only the branches the capture forked
+    const int used = std::min(NT, kMaxBranches);   // join only the branches the capture forked
     for (int k = 0; k < used && err == hipSuccess; ++k) {
         err = hipEventRecord(S->fork_ev[1 + k], S->branch[k]);
         if (err == hipSuccess) err = hipStreamWaitEvent(S->hs, S->fork_ev[1 + k], 0);
@@ -325,7 +348,8 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
         return RF_OK;
     }
     const int C = (int)S->classes.size();
-    for (int t = 0; t <= C; ++t) {
+    const int NT = C + (int)S->ddc_classes.size();
+    for (int t = 0; t < NT; ++t) {
         rfk::GroupHeader *h = hdr_at(b.host, S->region, t);
         h->count = 0;
         h->total = 0;
@@ -345,8 +369,9 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
             h->count++;
         }
         if (s->ddc) {
-            rfk::GroupHeader *h = hdr_at(b.host, S->region, C);
-            rfk::DdcItem &it = items_at<rfk::DdcItem>(b.host, S->region, C)[h->count];
+            const int t = C + ddc_class_index(S, s->ntones);
+            rfk::GroupHeader *h = hdr_at(b.host, S->region, t);
+            rfk::DdcItem &it = items_at<rfk::DdcItem>(b.host, S->region, t)[h->count];
             it.a = dl[i];
             it.unit_begin = h->total;
             h->total += rfk::ddc_group_units(dl[i]);
@@ -360,9 +385,9 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
         }
         if (hipGraphLaunch(b.exec, S->hs) != hipSuccess) return set_error(RF_EDEVICE, "hipGraphLaunch failed");
     } else {
-        hipError_t e = hipMemcpyAsync(b.dev, b.host, S->region * (C + 1), hipMemcpyHostToDevice, S->hs);
+        hipError_t e = hipMemcpyAsync(b.dev, b.host, S->region * NT, hipMemcpyHostToDevice, S->hs);
         if (e != hipSuccess) return set_error(RF_EDEVICE, "table upload failed");
-        for (int t = 0; t <= C; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const rfk::GroupHeader *hh = hdr_at(b.host, S->region, t);
             if (hh->count == 0) continue;
             const rfk::GroupHeader *hd = hdr_at(b.dev, S->region, t);
@@ -372,7 +397,8 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
                                           items_at<rfk::PfbItem>(b.dev, S->region, t), grid, S->hs);
             } else {
                 const int grid = (int)std::min<int64_t>(hh->total, S->cus);
-                e = rfk::launch_ddc_group(hd, items_at<rfk::DdcItem>(b.dev, S->region, t), grid, S->hs);
+                e = rfk::launch_ddc_group(S->ddc_classes[t - C], hd, items_at<rfk::DdcItem>(b.dev, S->region, t),
+                                          grid, S->hs);
             }
             if (e != hipSuccess) return set_error(RF_EDEVICE, "grouped launch failed");
         }
@@ -515,9 +541,10 @@ int rfs_create(rfs_t *out, uint64_t hbm_budget_bytes, int32_t mode, int32_t max_
         ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
         if (ok) S->fork_ev.push_back(ev);
     }
-    // item tables sized for every open stream in up to max_streams classes + DDC
+    // item tables sized for every open stream in up to max_streams PFB classes
+    // and the five DDC work-group sizes
     S->region = region_bytes(max_streams);
-    const size_t bytes = S->region * (size_t)(max_streams + 1);
+    const size_t bytes = S->region * (size_t)(max_streams + 5);
     for (int k = 0; ok && k < 2; ++k) {
         Blob &b = S->blobs[k];
         b.bytes = bytes;
