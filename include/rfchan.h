@@ -306,7 +306,8 @@ int ddc_tuned_config(rf_ddc_t ddc, int32_t *grid);
  * device.  Requests (one buffer of a stream each) are queued as they arrive; a
  * scheduler thread continuously forms batches from the oldest pending buffer
  * of every stream that has a free output slot, and runs each batch as grouped
- * kernels (one per channel/tap class plus one for all DDC banks) whose
+ * kernels (one per PFB channel/tap class, one per DDC work-group size, which
+ * follows the bank's tone count as in a single-stream launch) whose
  * work-groups stride over the buffers of all streams in the batch.  Requests
  * that arrive while a batch is on the GPU join the next one.  Streams are
  * admitted by their device-memory footprint against a budget.
