@@ -141,8 +141,8 @@ def test_p5_bin_centred_tone_lands_in_one_channel(N, M, win):
 
 @pytest.mark.parametrize("N,M,win,adj_db", [(64, 4, "hann", -44.4), (1024, 8, "kaiser", -93.6)])
 def test_p5_adjacent_channel_rejection(N, M, win, adj_db):
-    # survey design property of the two prototypes (checked independently of the oracle
-    # through the taps' DTFT), then the oracle's output must show it
+    # adjacent-channel rejection of the two prototypes, computed in FP64 from the
+    # taps' DTFT independently of the oracle; the oracle's output must show it
     h = siggen.pfb_prototype(N, M, win, 9.0)
     x = tone(N, 3, 1.0, 0.0, N * (M + 1))
     X = oracle.pfb(h, N, M, x=x)
