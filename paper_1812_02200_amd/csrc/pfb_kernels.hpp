@@ -211,15 +211,17 @@ __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
     if constexpr (!LAST) group_sync<XW>();
 }
 
-template <int N, int NS, bool NT_STORE, bool SEL>
+// STAGED: the last pass leaves the spectrum in LDS (natural bin order) for
+// the caller to copy out.
+template <int N, int NS, bool NT_STORE, bool SEL, bool STAGED = false>
 __device__ __forceinline__ void fft_passes(cf *lds, int fb, int tl, const cf *twl,
                                            const cf *__restrict__ twg, float *__restrict__ outf,
                                            bool valid, const int32_t *__restrict__ sel, int nsel)
 {
     if constexpr (NS < N) {
         constexpr int R = pass_radix(N, NS);
-        fft_pass<N, R, NS, NS * R == N, NT_STORE, SEL>(lds, fb, tl, twl, twg, outf, valid, sel);
-        fft_passes<N, NS * R, NT_STORE, SEL>(lds, fb, tl, twl, twg, outf, valid, sel, nsel);
+        fft_pass<N, R, NS, NS * R == N, NT_STORE, SEL || STAGED>(lds, fb, tl, twl, twg, outf, valid, sel);
+        fft_passes<N, NS * R, NT_STORE, SEL, STAGED>(lds, fb, tl, twl, twg, outf, valid, sel, nsel);
     } else if constexpr (SEL) {
         // the spectrum is in LDS: the team gathers the chosen bins into
         // consecutive columns (sel = the bins, in output order)
@@ -303,6 +305,48 @@ __device__ __forceinline__ void shift_window(FirState<N, M> &st, const uint32_t 
         for (int k = 0; k < 4; ++k) st.xw[W - 4 + i][k].set(pre[i][k]);
 }
 
+// Small N: a frame's team is one or two threads, so stores straight from the
+// last pass would put 8-byte pieces of many frames into each wave store.  The
+// spectra stay in LDS instead and each wave writes out its own lane groups'
+// four frames (4N consecutive values in the output) with consecutive lanes on
+// consecutive values.  Frames at or past `f1` of a lane group's run are not
+// written.
+template <int N>
+struct PfbStage {
+    static constexpr bool ON = N <= 32;
+};
+
+template <int N, bool NT_STORE>
+__device__ __forceinline__ void staged_copy(const cf *lds, float *__restrict__ out, int64_t lg_base, int RL,
+                                            int ph, int64_t F)
+{
+    constexpr int L = PfbPlan<N>::L;
+    static_assert(L <= 64 && 64 % L == 0, "lane groups inside one wave");
+    constexpr int LGW = 64 / L;   // lane groups per wave
+    constexpr int CH = 4 * N;     // values of a lane group's four frames
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll 1
+    for (int i = 0; i < LGW; ++i) {
+        const int g = wv * LGW + i;
+        const int64_t run0 = (lg_base + g) * RL;
+        const int64_t f1 = run0 + RL < F ? run0 + RL : F;
+        const int64_t fg = run0 + 4 * ph;
+#pragma unroll
+        for (int e = lane; e < CH; e += 64) {
+            if (fg + e / N < f1) {
+                const cf x = lds[lpad(4 * g * N + e)];
+                f2v o = {x.x, x.y};
+                f2v *dst = (f2v *)(out + 2 * (fg * N + e));
+                if constexpr (NT_STORE)
+                    __builtin_nontemporal_store(o, dst);
+                else
+                    *dst = o;
+            }
+        }
+    }
+}
+
 template <int N, int V>
 struct PfbVariant {
     static constexpr bool DBUF = (V & 1) && N <= 1024 && !PfbPlan<N>::LG_IN_WAVE;
@@ -346,6 +390,7 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     // output row length: all N bins, or the chosen channels (variant bit 8:
     // a.sel lists the bins in output order; compiled only into that variant)
     constexpr bool SEL = (V & 8) != 0;
+    constexpr bool STAGE = PfbStage<N>::ON && !SEL;
     const int32_t *sel = SEL ? a.sel : nullptr;
     const int64_t ldo = SEL ? (int64_t)a.nsel : (int64_t)N;
 
@@ -393,8 +438,12 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             }
             fir_phase<N, M>(st, lds, g, c);
             group_sync<!P::LG_IN_WAVE>();
-            fft_passes<N, 4, VV::NT_STORE, SEL>(lds, slot * N, tl, twl, twg,
-                                           a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, sel, a.nsel);
+            fft_passes<N, 4, VV::NT_STORE, SEL, STAGE>(lds, slot * N, tl, twl, twg,
+                                                  a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, sel, a.nsel);
+            if constexpr (STAGE) {
+                wave_fence();
+                staged_copy<N, VV::NT_STORE>(lds, a.out, (int64_t)lwg * P::NLG, RL, ph, F);
+            }
             if constexpr (SYNC2) group_sync<true>();
             else wave_fence();
             if (more) shift_window<N, M>(st, pre);
@@ -432,8 +481,12 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             {
                 const int64_t f = f0t + 4 * ph + q2;
                 const bool valid = f < f1t;
-                fft_passes<N, 4, VV::NT_STORE, SEL>(lds, slot * N, tl, twl, twg,
-                                               a.out + 2 * (valid ? f : 0) * ldo, valid, sel, a.nsel);
+                fft_passes<N, 4, VV::NT_STORE, SEL, STAGE>(lds, slot * N, tl, twl, twg,
+                                                      a.out + 2 * (valid ? f : 0) * ldo, valid, sel, a.nsel);
+            }
+            if constexpr (STAGE) {
+                wave_fence();
+                staged_copy<N, VV::NT_STORE>(lds, a.out, (int64_t)lwg * P::NLG, RL, ph, F);
             }
             if constexpr (SYNC2) group_sync<true>();
             else wave_fence();
