@@ -432,6 +432,8 @@ static hipError_t launch_step_u(const StepDesc &d, int64_t N, int64_t total, hip
 static hipError_t launch_step(const StepDesc &d, int64_t N, int64_t total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
+    // the kernel addresses a tile's frames through a range below kOff bytes
+    if ((int64_t)(d.TB / d.C + 2) * N * (int64_t)sizeof(cf) >= kOff) return hipErrorInvalidValue;
     const int64_t pts = (int64_t)d.TB * d.L;
     if (pts <= 8 * kStepWG) return launch_step_u<8>(d, N, total, s);
     if (pts <= 16 * kStepWG) return launch_step_u<16>(d, N, total, s);
