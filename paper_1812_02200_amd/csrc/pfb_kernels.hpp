@@ -34,7 +34,9 @@
 // Variant bits (kernel template parameter V, chosen at launch):
 //   1: two LDS phase buffers, one work-group barrier per phase (N <= 1024);
 //   2: ordinary (write-back) stores instead of non-temporal stores;
-//   8: only chosen channels are stored (bin list in PfbLaunch::sel).
+//   8: only chosen channels are stored (bin list in PfbLaunch::sel);
+//  16: even work-groups walk their run backwards, so that neighbouring runs
+//      read their shared blocks together (fast path; same results).
 #pragma once
 #include "fft_device.hpp"
 #include "rf_internal.hpp"
@@ -420,7 +422,60 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     const int64_t f1t = (f0t + RL < F) ? f0t + RL : F;
     __syncthreads();   // twiddle tables staged
 
-    if (fast) {
+    if constexpr ((V & 16) != 0) {
+        if (fast) {
+            // Variant bit 16: even work-groups walk their run backwards (last
+            // phase first), so two neighbouring runs read the M-1 blocks they
+            // share at about the same time and the second read hits the cache.
+            // Each frame's sum is formed exactly as in the forward walk.
+            const bool back = (lwg & 1) == 0;
+            const uint32_t *base = vs.in + (f0 * N - vs.H) + c;
+            const int64_t b0 = back ? 4 * (int64_t)(nph - 1) : 0;   // first window block
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) st.xw[i][k].set(base[(b0 + i) * N + k * L]);
+#pragma unroll 1
+            for (int it = 0; it < nph; ++it) {
+                const int ph = back ? nph - 1 - it : it;
+                cf *lds = lds_all + (VV::DBUF ? (it & 1) * P::LDS : 0);
+                uint32_t pre[4][4];
+                const bool more = it + 1 < nph;
+                if (more) {
+                    const uint32_t *p = base + (int64_t)(back ? 4 * ph - 4 : 4 * ph + W) * N;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) pre[i][k] = p[i * N + k * L];
+                }
+                fir_phase<N, M>(st, lds, g, c);
+                group_sync<!P::LG_IN_WAVE>();
+                fft_passes<N, 4, VV::NT_STORE, SEL, STAGE>(lds, slot * N, tl, twl, twg,
+                                                      a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, sel, a.nsel);
+                if constexpr (STAGE) {
+                    wave_fence();
+                    staged_copy<N, VV::NT_STORE>(lds, a.out, (int64_t)lwg * P::NLG, RL, ph, F);
+                }
+                if constexpr (SYNC2) group_sync<true>();
+                else wave_fence();
+                if (more) {
+                    if (back) {
+#pragma unroll
+                        for (int i = W - 1; i >= 4; --i)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) st.xw[i][k] = st.xw[i - 4][k];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) st.xw[i][k].set(pre[i][k]);
+                    } else {
+                        shift_window<N, M>(st, pre);
+                    }
+                }
+            }
+        }
+    }
+    if (fast && (V & 16) == 0) {
         // block b of this lane group starts at in + (f0 + b)*N - H
         const uint32_t *base = vs.in + (f0 * N - vs.H) + c;
 #pragma unroll
@@ -461,7 +516,7 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             phase(ph + 2);
         }
         for (; ph < nph; ++ph) phase(ph);
-    } else {
+    } else if (!fast) {
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             uint32_t w[4];

@@ -1,6 +1,6 @@
 // Instantiations of the fused PFB kernel for N = 1024 (M = 1..16), all bins or
 // chosen channels, plus the tunable variants of the M = 8 kernel
-// (double-buffered LDS, store type).
+// (double-buffered LDS, store type, alternate run directions).
 #include "pfb_kernels.hpp"
 
 namespace rfk {
@@ -13,6 +13,8 @@ hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s)
         case 1: return launch_pfb_nmv<1024, 8, 1>(a, s);
         case 2: return launch_pfb_nmv<1024, 8, 2>(a, s);
         case 3: return launch_pfb_nmv<1024, 8, 3>(a, s);
+        case 16: return launch_pfb_nmv<1024, 8, 16>(a, s);
+        case 17: return launch_pfb_nmv<1024, 8, 17>(a, s);
         default: break;
         }
     }

@@ -1112,7 +1112,10 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     a.N = p->N;
     a.M = p->M;
     static const int rls[] = {8, 12, 16, 20, 24, 32, 48, 64};
-    const int nvar = (p->mode == RF_DFT_FFT_F32 && p->N == 1024 && p->M == 8) ? 2 : 1;
+    // kernel variants tried for N = 1024, M = 8: single or double-buffered
+    // LDS, each with forward runs or with alternate runs walked backwards
+    static const int vars[] = {0, 1, 16, 17};
+    const int nvar = (p->mode == RF_DFT_FFT_F32 && p->N == 1024 && p->M == 8) ? 4 : 1;
     double best = 1e30;
     int best_rl = 0, best_var = 0;
     int k = 0;
@@ -1120,7 +1123,8 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     // transient does not decide the choice
     for (int pass = 0; pass < 2 && rc == RF_OK; ++pass)
     for (int rl : rls) {
-        for (int var = 0; var < nvar; ++var) {
+        for (int vi = 0; vi < nvar; ++vi) {
+            const int var = vars[vi];
             a.run_len = rl;
             a.variant = var;
             double us = 0;

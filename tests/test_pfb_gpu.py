@@ -209,12 +209,38 @@ def test_pfb_tune_keeps_results_bit_exact(tmp_path, monkeypatch):
     p = rf.Pfb(N, M, h, max_samples_per_call=n)
     us, rl, var = p.tune(n)
     log("tuned: %.1f us, run_len=%d variant=%d" % (us, rl, var))
-    assert us > 0 and rl % 4 == 0 and var in (0, 1)
+    assert us > 0 and rl % 4 == 0 and var in (0, 1, 16, 17)
     got = run_pfb(p, d, [n], torch)
     assert np.array_equal(got.view(np.uint64), base.view(np.uint64))
     q = rf.Pfb(N, M, h, max_samples_per_call=n)
     assert q.apply_tuned(n) and not q.apply_tuned(n + 1)
     assert (tmp_path / "tune.txt").read_text().startswith("pfb gfx950 1024 8 0 %d" % n)
+
+
+def test_pfb_variants_bit_exact(monkeypatch):
+    """Every launch variant of the N=1024, M=8 kernel (LDS buffering, run
+    direction) and run length computes every frame the same way, across
+    buffer splits that exercise the history and tail paths."""
+    rf = _rf()
+    import torch
+    N, M = 1024, 8
+    h = siggen.pfb_prototype(N, M, "kaiser")
+    n = N * 1500 + 77
+    iq = siggen.StreamSpec(41, siggen.pfb_small().stream.tones, 400.0).iq(0, n)
+    d = to_dev(iq)
+    splits = [N * 700 + 5, N * 3 + 1, n - (N * 700 + 5) - (N * 3 + 1)]
+    base = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, splits, torch)
+    for var in (1, 16, 17):
+        for rl in (8, 12, 32):
+            monkeypatch.setenv("RFCHAN_PFB_VARIANT", str(var))
+            monkeypatch.setenv("RFCHAN_PFB_RUN_LEN", str(rl))
+            p = rf.Pfb(N, M, h, max_samples_per_call=n)
+            monkeypatch.delenv("RFCHAN_PFB_VARIANT")
+            monkeypatch.delenv("RFCHAN_PFB_RUN_LEN")
+            assert p.tuned_config() == (rl, var)
+            got = run_pfb(p, d, splits, torch)
+            log("variant %d run length %d" % (var, rl))
+            assert np.array_equal(got.view(np.uint64), base.view(np.uint64)), (var, rl)
 
 
 @pytest.mark.slow
