@@ -1,6 +1,7 @@
 // Instantiations of the fused PFB kernel for N = 1024 (M = 1..16), all bins or
 // chosen channels, plus the tunable variants of the M = 8 kernel
-// (double-buffered LDS, store type, alternate run directions).
+// (double-buffered LDS, store type, alternate run directions) and alternate
+// run directions at M = 4.
 #include "pfb_kernels.hpp"
 
 namespace rfk {
@@ -18,6 +19,7 @@ hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s)
         default: break;
         }
     }
+    if (a.M == 4 && a.variant == 16) return launch_pfb_nmv<1024, 4, 16>(a, s);
     return launch_pfb_nv<1024, 0>(a, s);
 }
 
