@@ -8,7 +8,10 @@ namespace rfk {
 
 hipError_t launch_pfb_n1024(const PfbLaunch &a, hipStream_t s)
 {
-    if (a.sel) return launch_pfb_nv<1024, 8>(a, s);
+    if (a.sel) {
+        if (a.M == 8 && (a.variant & 16)) return launch_pfb_nmv<1024, 8, 24>(a, s);
+        return launch_pfb_nv<1024, 8>(a, s);
+    }
     if (a.M == 8) {
         switch (a.variant) {
         case 1: return launch_pfb_nmv<1024, 8, 1>(a, s);

@@ -241,6 +241,12 @@ def test_pfb_variants_bit_exact(monkeypatch):
             got = run_pfb(p, d, splits, torch)
             log("variant %d run length %d" % (var, rl))
             assert np.array_equal(got.view(np.uint64), base.view(np.uint64)), (var, rl)
+            # chosen channels under the same launch shape: the full spectrum's columns
+            ch = np.array([5, 1023, 0, 512, 77], dtype=np.int32)
+            p.reset()
+            p.set_channels(ch)
+            sub = run_pfb(p, d, splits, torch)
+            assert np.array_equal(sub.view(np.uint64), base[:, ch].copy().view(np.uint64)), (var, rl)
 
 
 @pytest.mark.slow
