@@ -424,11 +424,14 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
 
     if constexpr ((V & 16) != 0) {
         if (fast) {
-            // Variant bit 16: even work-groups walk their run backwards (last
-            // phase first), so two neighbouring runs read the M-1 blocks they
-            // share at about the same time and the second read hits the cache.
-            // Each frame's sum is formed exactly as in the forward walk.
-            const bool back = (lwg & 1) == 0;
+            // Variant bit 16: even runs are walked backwards (last phase
+            // first), so two neighbouring runs read the M-1 blocks they share
+            // at about the same time and the second read hits the cache.  Each
+            // frame's sum is formed exactly as in the forward walk.  (A lane
+            // group is at least one whole wave here, N >= 256, so the choice
+            // is uniform per wave.)
+            static_assert(P::L >= 64, "lane groups of whole waves");
+            const bool back = (((int64_t)lwg * P::NLG + g) & 1) == 0;
             const uint32_t *base = vs.in + (f0 * N - vs.H) + c;
             const int64_t b0 = back ? 4 * (int64_t)(nph - 1) : 0;   // first window block
 #pragma unroll

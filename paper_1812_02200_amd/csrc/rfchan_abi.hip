@@ -1114,11 +1114,12 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     static const int rls[] = {8, 12, 16, 20, 24, 32, 48, 64};
     // kernel variants tried: for N = 1024, M = 8 single or double-buffered
     // LDS, each with forward runs or with alternate runs walked backwards;
-    // for N = 1024 at M = 4 and N = 2048 at M = 4, 8 the two run orders
+    // for N = 256, 512, 2048 at M = 4, 8 and N = 1024 at M = 4 the two run orders
     static const int vars8[] = {0, 1, 16, 17}, vars2[] = {0, 16};
     const bool fft = p->mode == RF_DFT_FFT_F32;
     const bool v4 = fft && p->N == 1024 && p->M == 8;
-    const bool v2 = fft && ((p->N == 1024 && p->M == 4) || (p->N == 2048 && (p->M == 4 || p->M == 8)));
+    const bool v2 = fft && !v4 && (p->M == 4 || p->M == 8) &&
+                    (p->N == 256 || p->N == 512 || p->N == 1024 || p->N == 2048);
     const int *vars = v4 ? vars8 : vars2;
     const int nvar = v4 ? 4 : v2 ? 2 : 1;
     double best = 1e30;

@@ -217,20 +217,21 @@ def test_pfb_tune_keeps_results_bit_exact(tmp_path, monkeypatch):
     assert (tmp_path / "tune.txt").read_text().startswith("pfb gfx950 1024 8 0 %d" % n)
 
 
-def test_pfb_variants_bit_exact(monkeypatch):
-    """Every launch variant of the N=1024, M=8 kernel (LDS buffering, run
-    direction) and run length computes every frame the same way, across
-    buffer splits that exercise the history and tail paths."""
+@pytest.mark.parametrize("N,M,variants", [(1024, 8, (1, 16, 17)), (256, 8, (16,)), (512, 4, (16,)),
+                                          (2048, 4, (16,))])
+def test_pfb_variants_bit_exact(monkeypatch, N, M, variants):
+    """Every launch variant (LDS buffering, run direction) and run length
+    computes every frame the same way, across buffer splits that exercise the
+    history and tail paths."""
     rf = _rf()
     import torch
-    N, M = 1024, 8
     h = siggen.pfb_prototype(N, M, "kaiser")
     n = N * 1500 + 77
     iq = siggen.StreamSpec(41, siggen.pfb_small().stream.tones, 400.0).iq(0, n)
     d = to_dev(iq)
     splits = [N * 700 + 5, N * 3 + 1, n - (N * 700 + 5) - (N * 3 + 1)]
     base = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, splits, torch)
-    for var in (1, 16, 17):
+    for var in variants:
         for rl in (8, 12, 32):
             monkeypatch.setenv("RFCHAN_PFB_VARIANT", str(var))
             monkeypatch.setenv("RFCHAN_PFB_RUN_LEN", str(rl))
@@ -242,7 +243,7 @@ def test_pfb_variants_bit_exact(monkeypatch):
             log("variant %d run length %d" % (var, rl))
             assert np.array_equal(got.view(np.uint64), base.view(np.uint64)), (var, rl)
             # chosen channels under the same launch shape: the full spectrum's columns
-            ch = np.array([5, 1023, 0, 512, 77], dtype=np.int32)
+            ch = np.array([5, N - 1, 0, N // 2, 77], dtype=np.int32)
             p.reset()
             p.set_channels(ch)
             sub = run_pfb(p, d, splits, torch)
