@@ -101,6 +101,28 @@ def test_ten_million_channels_sampled():
     assert err_fs(y[:, bins], ref, h.sum()) <= 1e-5
 
 
+def test_fig3_shape_production_stream_sampled():
+    """N = 10^5, M = 8 on the production stream in 2^24-sample buffers (the
+    shape the benchmark times: hundreds of frames per call, the persistent
+    step grid walking many tiles): sampled bins of every frame of the first
+    2^25 samples against the oracle's direct DFT at those bins."""
+    rf = _rf()
+    import torch
+    N, M = 100000, 8
+    buf = 1 << 24
+    h = proto(N, M)
+    w = siggen.pfb_production()
+    d = siggen.iq_torch(w.stream, 0, 2 * buf)
+    p = rf.Pfb(N, M, h, max_samples_per_call=buf)
+    y = run_pfb(p, d, [buf, buf], torch)
+    iq = d.cpu().numpy()
+    assert y.shape[0] == oracle.pfb_nframes(2 * buf, N, M)
+    bins = np.unique(np.concatenate([np.random.default_rng(5).integers(0, N, 12), [0, 1, N // 2, N - 1]]))
+    log("fig3 shape: %d frames, %d bins" % (y.shape[0], bins.size))
+    ref = oracle.pfb_channels(f32(h), N, M, bins, iq=iq)
+    assert err_fs(y[:, bins], ref, h.sum()) <= 1e-5
+
+
 def test_small_non_power_of_two_with_many_frames():
     """N = 18: a buffer of 2^26 samples holds ~3.7M frames, more 32-frame
     chunks than one grid dimension covers (the fold strides over the rest);
