@@ -251,11 +251,13 @@ def test_pfb_variants_bit_exact(monkeypatch, N, M, variants):
 
 
 @pytest.mark.slow
-def test_pfb_production_full_size_sampled():
+def test_pfb_production_full_size_sampled(monkeypatch):
     """N=1024, M=8, Kaiser(9): 2^28 samples in 16 buffers of 2^24 -> 262137 frames.
 
-    Inputs generated on the device (same recipe as the benchmark); sampled frames,
-    including every buffer boundary, are checked against the oracle.
+    Inputs generated on the device (same recipe as the benchmark), in the launch
+    configuration the benchmark's tuner picks (run length 32, double-buffered
+    LDS, alternate run directions); sampled frames, including every buffer
+    boundary, are checked against the oracle.
     """
     rf = _rf()
     import torch
@@ -263,7 +265,12 @@ def test_pfb_production_full_size_sampled():
     log("pfb production: generating 2^28 samples on the device")
     d = siggen.iq_torch(w.stream, 0, w.nsamples)
     torch.cuda.synchronize()
+    monkeypatch.setenv("RFCHAN_PFB_RUN_LEN", "32")
+    monkeypatch.setenv("RFCHAN_PFB_VARIANT", "17")
     p = rf.Pfb(w.N, w.M, w.h, max_samples_per_call=w.buffer)
+    monkeypatch.delenv("RFCHAN_PFB_RUN_LEN")
+    monkeypatch.delenv("RFCHAN_PFB_VARIANT")
+    assert p.tuned_config() == (32, 17)
     total = p.frames_for(w.nsamples)
     out = torch.empty((262137, w.N), dtype=torch.complex64, device="cuda")
     pos, f = 0, 0
