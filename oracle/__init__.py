@@ -177,6 +177,17 @@ def pfb_fold(h, N: int, M: int, iq=None, x=None, frames=None) -> np.ndarray:
     return out
 
 
+def pfb_fold_fft(h, N: int, M: int, iq=None, x=None, frames=None) -> np.ndarray:
+    """Every bin of the given frames (all valid frames by default), complex128
+    [frames x N]: the oracle's FP64 fold, then numpy's FP64 FFT as the DFT step
+    (paper Sec. III.A: X_p[k] = sum_n v_p[n] exp(-2 pi i k n / N); a library
+    FFT of any length, including the large and non-power-of-two N of Fig. 3,
+    where the oracle's own direct DFT is O(N^2) per frame).  Pinned against
+    the direct DFT at sampled bins and the radix-2 oracle path."""
+    v = pfb_fold(h, N, M, iq=iq, x=x, frames=frames)
+    return np.fft.fft(v, axis=1)
+
+
 def nco_table() -> np.ndarray:
     """complex128[65536]: cos + i sin at 2 pi idx / 2^16 (FP64)."""
     tab = np.empty(65536, dtype=np.complex128)

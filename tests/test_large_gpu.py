@@ -1,19 +1,31 @@
 """Large and non-power-of-two channel counts (paper Sec. III.A, Fig. 3:
 N = 10^5) on the GPU: fold pass + four-step FFT, against the FP64 oracle.
 
-Full comparisons where the oracle is fast (its FFT for powers of two, its
-direct DFT for N <= a few thousand); otherwise sampled bins of every frame by
-the oracle's direct DFT at those bins.  Bar: RMS error <= 1e-5 of a full-scale
-tone's output; buffer splits bit-identical.
+Every bin of every frame (or of sampled frames where the stream holds
+millions) is compared with the oracle: its direct DFT where N is a few
+thousand, otherwise its FP64 fold followed by numpy's FP64 FFT
+(``oracle.pfb_fold_fft``).  Bars, as for every PFB path: RMS error <= 1e-5 of a
+full-scale tone's output, and the regression guard ||e|| / ||y_ref|| <= 1e-6
+over whole frames.  The bins of the tones and their two neighbours, and the
+remaining (noise-only) bins, are also checked on their own: an FFT's rounding
+error is spread over all bins at a level set by the frame's total energy, so
+bins far below the frame's RMS level could see a larger relative error than
+the frame as a whole; measured, they stay within the same 1e-6 (about 4e-7 at
+N = 10^7), so both groups are held to it -- a wrong twiddle or index in any
+part of the spectrum gives errors of order one there.  Buffer splits are
+bit-identical.
 """
 import numpy as np
 import pytest
 
 import oracle
 import siggen
-from gpu_util import err_fs, f32, log, need_gpu, run_pfb, to_dev
+from gpu_util import err_fs, err_rel, f32, log, need_gpu, run_pfb, to_dev
 
 pytestmark = pytest.mark.gpu
+
+TOL_FS = 1e-5
+TOL_REL = 1e-6
 
 
 def _rf():
@@ -27,10 +39,37 @@ def proto(N, M):
 
 
 def stream(n, seed, N):
+    """12 tones (bin-centred and off-grid) over noise; returns (iq, tone bins)."""
     rng = np.random.default_rng(seed)
-    words = np.array([siggen.bin_word(k + 0.25 * (k % 4), N) for k in rng.integers(0, N, 12)], dtype=np.uint64)
+    ks = rng.integers(0, N, 12)
+    words = np.array([siggen.bin_word(k + 0.25 * (k % 4), N) for k in ks], dtype=np.uint64)
     tones = siggen.ToneSet(words, np.full(12, 600.0), rng.uniform(0, 6.28, 12))
-    return siggen.StreamSpec(seed, tones, 700.0).iq(0, n)
+    return siggen.StreamSpec(seed, tones, 700.0).iq(0, n), ks
+
+
+def tone_bins_of_words(words, N):
+    """Nearest bin of each tuning word (word / 2^64 cycles per sample)."""
+    w = np.asarray(words, dtype=np.uint64)
+    return np.unique(np.rint(w.astype(np.float64) / 2.0 ** 64 * N).astype(np.int64) % N)
+
+
+def check(y, ref, h, tone_bins, label):
+    """Whole-frame bars plus the tone / quiet-bin split; logs every figure."""
+    assert y.shape == ref.shape, (y.shape, ref.shape)
+    N = ref.shape[1]
+    e, r = err_fs(y, ref, h.sum()), err_rel(y, ref)
+    near = np.zeros(N, bool)
+    for k in np.asarray(tone_bins, np.int64):
+        near[[(k - 1) % N, k % N, (k + 1) % N]] = True
+    r_tone = err_rel(y[:, near], ref[:, near])
+    r_quiet = err_rel(y[:, ~near], ref[:, ~near]) if (~near).any() else 0.0
+    emax = float(np.max(np.abs(np.asarray(y, np.complex128) - ref))) if ref.size else 0.0
+    log("%s: frames=%d err_fs=%.3g err_rel=%.3g tone-bins err_rel=%.3g quiet-bins err_rel=%.3g "
+        "max|e|=%.3g LSB" % (label, ref.shape[0], e, r, r_tone, r_quiet, emax))
+    assert e <= TOL_FS
+    assert r <= TOL_REL
+    assert r_tone <= TOL_REL
+    assert r_quiet <= TOL_REL
 
 
 @pytest.mark.parametrize("N,M", [(60, 4), (100, 1), (1000, 8), (1536, 2), (3000, 3)])
@@ -39,33 +78,25 @@ def test_one_step_non_power_of_two_full(N, M):
     import torch
     h = proto(N, M)
     n = N * M + 9 * N + 5
-    iq = stream(n, N + M, N)
+    iq, ks = stream(n, N + M, N)
     log("large one-step N=%d M=%d" % (N, M))
     y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), to_dev(iq), [n], torch)
     ref = oracle.pfb(f32(h), N, M, iq=iq)
-    assert y.shape == ref.shape
-    assert err_fs(y, ref, h.sum()) <= 1e-5
+    check(y, ref, h, ks, "one-step N=%d M=%d" % (N, M))
 
 
-@pytest.mark.parametrize("N,M,full", [(8192, 4, True), (6000, 2, False), (100000, 8, False),
-                                      (65536, 2, True), (1 << 20, 1, True)])
-def test_four_step(N, M, full):
+@pytest.mark.parametrize("N,M", [(8192, 4), (6000, 2), (100000, 8), (65536, 2), (1 << 20, 1)])
+def test_four_step(N, M):
     rf = _rf()
     import torch
     h = proto(N, M)
     n = N * M + 3 * N + 11
-    iq = stream(n, N % 1000 + M, N)
+    iq, ks = stream(n, N % 1000 + M, N)
     log("large four-step N=%d M=%d" % (N, M))
     y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), to_dev(iq), [n], torch)
     assert y.shape[0] == oracle.pfb_nframes(n, N, M)
-    if full:
-        ref = oracle.pfb(f32(h), N, M, iq=iq)
-        assert err_fs(y, ref, h.sum()) <= 1e-5
-    else:
-        rng = np.random.default_rng(N)
-        bins = np.unique(np.concatenate([rng.integers(0, N, 60), [0, 1, N - 1, N // 2]]))
-        ref = oracle.pfb_channels(f32(h), N, M, bins, iq=iq)
-        assert err_fs(y[:, bins], ref, h.sum()) <= 1e-5
+    ref = oracle.pfb_fold_fft(f32(h), N, M, iq=iq)
+    check(y, ref, h, ks, "four-step N=%d M=%d" % (N, M))
 
 
 def test_large_splits_bit_identical():
@@ -74,7 +105,8 @@ def test_large_splits_bit_identical():
     N, M = 100000, 4
     h = proto(N, M)
     n = N * M + 7 * N + 123
-    d = to_dev(stream(n, 7, N))
+    iq, _ = stream(n, 7, N)
+    d = to_dev(iq)
     whole = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, [n], torch)
     sizes = [N * M - 1, 1, 0, 2 * N + 17, N - 5, n]
     pos, tot = 0, []
@@ -87,25 +119,26 @@ def test_large_splits_bit_identical():
 
 
 @pytest.mark.slow
-def test_ten_million_channels_sampled():
+def test_ten_million_channels():
+    """N = 10^7 (the largest spectra of Sec. III.A), M = 2: both frames, every bin."""
     rf = _rf()
     import torch
     N, M = 10 ** 7, 2
     h = proto(N, M)
     n = N * M + N + 7
-    iq = stream(n, 77, N)
+    iq, ks = stream(n, 77, N)
     y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), to_dev(iq), [n], torch)
     assert y.shape == (2, N)
-    bins = np.unique(np.random.default_rng(1).integers(0, N, 24))
-    ref = oracle.pfb_channels(f32(h), N, M, bins, iq=iq)
-    assert err_fs(y[:, bins], ref, h.sum()) <= 1e-5
+    ref = oracle.pfb_fold_fft(f32(h), N, M, iq=iq)
+    check(y, ref, h, ks, "N=10^7 M=2")
 
 
-def test_fig3_shape_production_stream_sampled():
+def test_fig3_shape_production_stream():
     """N = 10^5, M = 8 on the production stream in 2^24-sample buffers (the
     shape the benchmark times: hundreds of frames per call, the persistent
-    step grid walking many tiles): sampled bins of every frame of the first
-    2^25 samples against the oracle's direct DFT at those bins."""
+    step grid walking many tiles): every bin of every frame of the first 2^25
+    samples against the oracle; the production stream's 1000 tones give the
+    tone bins."""
     rf = _rf()
     import torch
     N, M = 100000, 8
@@ -117,10 +150,8 @@ def test_fig3_shape_production_stream_sampled():
     y = run_pfb(p, d, [buf, buf], torch)
     iq = d.cpu().numpy()
     assert y.shape[0] == oracle.pfb_nframes(2 * buf, N, M)
-    bins = np.unique(np.concatenate([np.random.default_rng(5).integers(0, N, 12), [0, 1, N // 2, N - 1]]))
-    log("fig3 shape: %d frames, %d bins" % (y.shape[0], bins.size))
-    ref = oracle.pfb_channels(f32(h), N, M, bins, iq=iq)
-    assert err_fs(y[:, bins], ref, h.sum()) <= 1e-5
+    ref = oracle.pfb_fold_fft(f32(h), N, M, iq=iq)
+    check(y, ref, h, tone_bins_of_words(w.stream.tones.words, N), "fig3 production N=10^5 M=8")
 
 
 def test_small_non_power_of_two_with_many_frames():
@@ -140,4 +171,6 @@ def test_small_non_power_of_two_with_many_frames():
     assert y.shape == (F, N)
     frames = np.concatenate([np.arange(64), np.arange(F - 64, F), np.random.default_rng(3).integers(0, F, 128)])
     ref = oracle.pfb(f32(h), N, M, iq=iq, frames=frames)
-    assert err_fs(y[frames], ref, h.sum()) <= 1e-5
+    e, r = err_fs(y[frames], ref, h.sum()), err_rel(y[frames], ref)
+    log("N=18 M=3 sampled frames: err_fs=%.3g err_rel=%.3g" % (e, r))
+    assert e <= TOL_FS and r <= TOL_REL

@@ -69,6 +69,23 @@ def test_p2_pfb_dft_stage_matches_numpy_fft(N, M):
     assert relerr(X, np.fft.fft(V, axis=1)) < (1e-13 if N & (N - 1) == 0 else 1e-12)
 
 
+@pytest.mark.parametrize("N,M", [(1024, 4), (6000, 2), (100000, 1)])
+def test_p2_fold_fft_matches_direct_dft_at_sampled_bins(N, M):
+    # pfb_fold_fft (fold + numpy FFT, the full-spectrum reference for large N)
+    # against the oracle's direct DFT sum at sampled bins, and, for a power of
+    # two, against the oracle's own radix-2 path at every bin
+    iq = np.clip(np.rint(RNG.normal(0, 900, 2 * N * (M + 2))), -8192, 8191).astype(np.int16)
+    h = RNG.standard_normal(N * M)
+    X = oracle.pfb_fold_fft(h, N, M, iq=iq)
+    bins = np.unique(np.concatenate([RNG.integers(0, N, 12), [0, 1, N // 2, N - 1]]))
+    assert relerr(X[:, bins], oracle.pfb_channels(h, N, M, bins, iq=iq)) < 1e-11
+    if N & (N - 1) == 0:
+        assert relerr(X, oracle.pfb(h, N, M, iq=iq)) < 1e-13
+    # Parseval on every frame: sum_k |X_p[k]|^2 = N sum_n |v_p[n]|^2
+    V = oracle.pfb_fold(h, N, M, iq=iq)
+    assert np.allclose(np.sum(np.abs(X) ** 2, 1), N * np.sum(np.abs(V) ** 2, 1), rtol=1e-12)
+
+
 def test_p2_fold_brute_force_tiny():
     # N=4, M=3: v_p[n] = sum_m h[mN+n] x[pN+mN+n] written out for p = 1
     N, M = 4, 3
