@@ -122,6 +122,25 @@ int pfb_set_channels(rf_pfb_t pfb, const int32_t *channels, int32_t nsel);
 int pfb_process(rf_pfb_t pfb, const int16_t *iq_dev, uint64_t nsamples, float *out_dev,
                 uint64_t out_cap_frames, uint64_t *frames_out, void *hip_stream);
 
+/* pfb_process for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, results, ordering and errors are those of pfb_process, and the
+ * output is bit-identical to it; the only difference is where a large or
+ * non-power-of-two-N handle's kernels keep their scratch (the folded frames
+ * and the first FFT step's output): in a 64 MiB array that the library holds
+ * in each GPU's memory from its first use on that GPU until the process ends,
+ * shared by every such call on that GPU, instead of in the handle.  The call
+ * allocates nothing.  Power-of-two-N handles use no scratch and are processed
+ * exactly as by pfb_process.
+ *   RF_EINVAL when the call's frames need more than the 64 MiB: F * N * 8
+ *   bytes for one-step N, twice that (each part rounded up to 256 bytes) for
+ *   two-step N, with F = pfb_frames_for(nsamples); the handle is unchanged.
+ * Calls on one GPU that can overlap in time -- on different HIP streams,
+ * or from different threads -- race on the shared array; order them on one
+ * stream. */
+int pfb_process_static(rf_pfb_t pfb, const int16_t *iq_dev, uint64_t nsamples, float *out_dev,
+                       uint64_t out_cap_frames, uint64_t *frames_out, void *hip_stream);
+
 /* Counters of the stream so far (host-side, no sync). Any pointer may be NULL. */
 int pfb_counters(rf_pfb_t pfb, uint64_t *samples_in, uint64_t *frames_out,
                  uint64_t *history_samples);

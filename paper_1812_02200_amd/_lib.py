@@ -71,6 +71,7 @@ SIGNATURES = {
     "pfb_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _I32, _P, _I32, _U64]),
     "pfb_frames_for": (_U64, [_P, _U64]),
     "pfb_process": (ctypes.c_int, [_P, _P, _U64, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "pfb_process_static": (ctypes.c_int, [_P, _P, _U64, _P, _U64, ctypes.POINTER(_U64), _P]),
     "pfb_counters": (ctypes.c_int, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "pfb_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(_SZ)]),
     "pfb_set_state": (ctypes.c_int, [_P, _P, _SZ]),
@@ -228,6 +229,14 @@ class Pfb:
         got = _U64(0)
         check(lib().pfb_process(self._h, iq_ptr, nsamples, out_ptr, out_cap_frames,
                                 ctypes.byref(got), stream_handle), "pfb_process")
+        return got.value
+
+    def process_static_ptr(self, iq_ptr: int, nsamples: int, out_ptr: int, out_cap_frames: int,
+                           stream_handle: int) -> int:
+        """pfb_process_static: as process_ptr, scratch from the library's static array."""
+        got = _U64(0)
+        check(lib().pfb_process_static(self._h, iq_ptr, nsamples, out_ptr, out_cap_frames,
+                                       ctypes.byref(got), stream_handle), "pfb_process_static")
         return got.value
 
     def tune(self, nsamples: int, stream=None):

@@ -13,6 +13,7 @@
 
 #include <sys/stat.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -432,6 +433,97 @@ int pfb_process(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out
     if (rc) return rc;
     if (p->large)
         HIP_TRY(rfk::launch_pfb_large(a, p->lplan, p->lbuf, s), "pfb large-N launch");
+    else if (p->mode == RF_DFT_FFT_F32)
+        HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
+    else
+        HIP_TRY(rfk::launch_pfb_mfma(a, p->mode == RF_DFT_MFMA_BF16X2 ? rfk::RF_PREC_BF16 : rfk::RF_PREC_F16, s),
+                "pfb mfma kernel launch");
+    rfi::pfb_commit(p, a, nsamples, F, s);
+    if (frames_out) *frames_out = F;
+    return RF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- process call without allocation
+//
+// The large-N path's kernels work through two scratch arrays (the folded
+// frames and the first FFT step's output).  pfb_process_static takes them from
+// this file-scope device array instead of the handle's own buffers, so a
+// caller that cannot allocate (code under graph capture, serving loops) still
+// has a call whose scratch memory is fixed in advance.  Each GPU holds its own
+// copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the device that is current.
+namespace {
+
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on device `dev` (the current device), looked
+// up once per device.
+int static_scratch(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(RF_EUNSUPPORTED, "pfb_process_static: device index %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(RF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return RF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfb_process_static(rf_pfb_t p, const int16_t *iq_dev, uint64_t nsamples, float *out_dev,
+                       uint64_t out_cap_frames, uint64_t *frames_out, void *hip_stream)
+{
+    if (frames_out) *frames_out = 0;
+    rfk::PfbLaunch a;
+    uint64_t F = 0;
+    int rc = rfi::pfb_prepare(p, iq_dev, nsamples, out_dev, out_cap_frames, &a, &F);
+    if (rc || nsamples == 0) return rc;
+    size_t vbytes = 0;
+    if (p->large) {
+        // folded frames, then (two-step plans) the first step's output
+        vbytes = ((size_t)F * (size_t)p->N * sizeof(rfk::cf) + 255) & ~(size_t)255;
+        const size_t need = p->lplan.N2 > 1 ? 2 * vbytes : vbytes;
+        if (need > kStaticScratchBytes)
+            return fail(RF_EINVAL,
+                        "pfb_process_static: %llu frames of %d channels need %zu bytes of scratch, more than "
+                        "the %zu-byte static scratch (use pfb_process, or fewer samples per call)",
+                        (unsigned long long)F, p->N, need, kStaticScratchBytes);
+    }
+    DeviceGuard dg(p->device);
+    HIP_TRY(dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    rfk::LargeBuffers lb = p->lbuf;
+    if (p->large) {
+        void *base = nullptr;
+        if ((rc = static_scratch(p->device, &base))) return rc;
+        lb.v = reinterpret_cast<rfk::cf *>(base);
+        lb.y = reinterpret_cast<rfk::cf *>(static_cast<unsigned char *>(base) + vbytes);
+    }
+    rc = p->order.before(s);
+    if (rc) return rc;
+    if (p->large)
+        HIP_TRY(rfk::launch_pfb_large(a, p->lplan, lb, s), "pfb large-N launch");
     else if (p->mode == RF_DFT_FFT_F32)
         HIP_TRY(rfk::launch_pfb(a, s), "pfb kernel launch");
     else
