@@ -68,8 +68,8 @@ typedef struct rf_pfb *rf_pfb_t;
 
 /* DFT stage implementations. */
 #define RF_DFT_FFT_F32 0      /* FP32 FFT (radix-4/16 Stockham in LDS)                  */
-#define RF_DFT_MFMA_F16X2 1   /* DFT as GEMMs on FP16 MFMA, hi/lo split operands, N=256 */
-#define RF_DFT_MFMA_BF16X2 2  /* DFT as GEMMs on BF16 MFMA, hi/lo split operands, N=256 */
+#define RF_DFT_MFMA_F16X2 1   /* DFT as GEMMs on FP16 MFMA, hi/lo split operands, N=16..256 */
+#define RF_DFT_MFMA_BF16X2 2  /* DFT as GEMMs on BF16 MFMA, hi/lo split operands, N=16..256 */
 
 /* Create a channelizer on the current HIP device.
  *   out       receives the handle.
@@ -82,8 +82,16 @@ typedef struct rf_pfb *rf_pfb_t;
  *   ntaps     M: 1 <= M <= 16.
  *   proto     host array of N*M FP32 prototype taps h[0..N*M); copied, the
  *             caller may free it on return.
- *   dft_mode  one of RF_DFT_*; the MFMA modes need N == 256
- *             (RF_EUNSUPPORTED otherwise).
+ *   dft_mode  one of RF_DFT_*; the MFMA modes need N in {16, 32, 64, 128,
+ *             256} (RF_EUNSUPPORTED otherwise).  They factor N = 16 N2 into a
+ *             DFT16 product and a block-diagonal DFT_N2 product, each on MFMA
+ *             with both operands split into high and low half-precision parts
+ *             (hi*hi + hi*lo + lo*hi, FP32 accumulation).  The taps are
+ *             stored multiplied by an exact power of two, chosen from the
+ *             largest column sum of |h| so that no half-precision operand can
+ *             exceed 2^15 for any int16 input, and the outputs are scaled
+ *             back exactly: any finite prototype is accepted (RF_EUNSUPPORTED
+ *             only if that power of two would leave [2^-100, 2^100]).
  *   max_samples_per_call  largest nsamples a single pfb_process will accept
  *             (>= 1).  Bounds the work of one call; no memory scales with it.
  * Allocates all device state (taps, twiddles, two history buffers of N*M

@@ -41,10 +41,11 @@ void pfb_twiddle_fill(int N, float *tw)
 
 int pfb_default_run_len(int N, int M, int64_t F)
 {
-    (void)N;
     (void)M;
-    // Aim for about 1024 lane-group runs, between 8 and 64 frames each.
-    const int64_t target = 1024;
+    // Aim for at least 512 work-groups (two per CU), runs of 8 to 64 frames;
+    // a work-group holds max(1, 1024 / N) lane groups, each walking one run.
+    const int64_t nlg = N >= 1024 ? 1 : 1024 / N;
+    const int64_t target = 512 * nlg;
     int64_t rl = (F + target - 1) / target;
     if (rl < 8) rl = 8;
     if (rl > 64) rl = 64;

@@ -85,11 +85,15 @@ void pfb_twiddle_fill(int N, float *tw);
 
 hipError_t launch_pfb(const PfbLaunch &a, hipStream_t s);
 
-// DFT on MFMA with hi/lo half-precision operands (N = 256 only).
+// DFT on MFMA with hi/lo half-precision operands (N = 16 .. 256, powers of two).
+// Variant bit 32 adds the lo*lo product term.
 enum { RF_PREC_F16 = 1, RF_PREC_BF16 = 2 };
 hipError_t launch_pfb_mfma(const PfbLaunch &a, int prec, hipStream_t s);
 int pfb_mfma_table_floats();
-void pfb_mfma_table_fill(float *t);
+// Exponent e of the exact tap scale 2^e that keeps every half-precision GEMM
+// operand within 2^15 for any int16 input (false: no such e in [-100, 100]).
+bool pfb_mfma_scale_exponent(const float *h, int N, int M, int *e);
+void pfb_mfma_table_fill(int N, int scale_exp, float *t);
 // Frames per run and launch geometry the PFB launcher will use.
 int pfb_default_run_len(int N, int M, int64_t F);
 

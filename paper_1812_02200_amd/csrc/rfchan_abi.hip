@@ -287,10 +287,15 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         return fail(RF_EINVAL, "pfb_create: max_samples_per_call out of range");
     if (dft_mode != RF_DFT_FFT_F32 && dft_mode != RF_DFT_MFMA_F16X2 && dft_mode != RF_DFT_MFMA_BF16X2)
         return fail(RF_EINVAL, "pfb_create: unknown dft_mode %d", dft_mode);
-    if (dft_mode != RF_DFT_FFT_F32 && nchan != 256)
-        return fail(RF_EUNSUPPORTED, "pfb_create: the MFMA DFT modes support nchan=256 only");
+    if (dft_mode != RF_DFT_FFT_F32 && (!fused || nchan > 256))
+        return fail(RF_EUNSUPPORTED, "pfb_create: the MFMA DFT modes support nchan = 16, 32, 64, 128, 256");
     for (int i = 0; i < nchan * ntaps; ++i)
         if (!isfinite(proto[i])) return fail(RF_EINVAL, "pfb_create: proto[%d] is not finite", i);
+    // MFMA modes: taps scaled by 2^e (exact) so that no half-precision operand
+    // can overflow; the kernel scales its outputs back by 2^-e
+    int mfma_exp = 0;
+    if (dft_mode != RF_DFT_FFT_F32 && !rfk::pfb_mfma_scale_exponent(proto, nchan, ntaps, &mfma_exp))
+        return fail(RF_EUNSUPPORTED, "pfb_create: taps too large for the half-precision MFMA DFT");
 
     rf_pfb *p = new (std::nothrow) rf_pfb;
     if (!p) return fail(RF_ENOMEM, "pfb_create: host allocation");
@@ -346,17 +351,28 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         pfb_free(p);
         return fail(RF_ENOMEM, "pfb_create: host allocation");
     }
-    if (dft_mode == RF_DFT_FFT_F32)
+    float *taps = (float *)malloc(sizeof(float) * span);
+    if (!taps) {
+        free(tw);
+        pfb_free(p);
+        return fail(RF_ENOMEM, "pfb_create: host allocation");
+    }
+    if (dft_mode == RF_DFT_FFT_F32) {
         rfk::pfb_twiddle_fill(nchan, tw);
-    else
-        rfk::pfb_mfma_table_fill(tw);
+        memcpy(taps, proto, sizeof(float) * span);
+    } else {
+        rfk::pfb_mfma_table_fill(nchan, mfma_exp, tw);
+        for (size_t i = 0; i < span; ++i) taps[i] = ldexpf(proto[i], mfma_exp);
+    }
     if ((rc = dev_alloc(&p->d_taps, span, "taps")) || (rc = dev_alloc(&p->d_tw, 2 * (size_t)ntw, "twiddles")) ||
         (rc = dev_alloc(&p->d_hist[0], span, "history")) || (rc = dev_alloc(&p->d_hist[1], span, "history"))) {
         free(tw);
+        free(taps);
         pfb_free(p);
         return rc;
     }
-    e = hipMemcpy(p->d_taps, proto, span * sizeof(float), hipMemcpyHostToDevice);
+    e = hipMemcpy(p->d_taps, taps, span * sizeof(float), hipMemcpyHostToDevice);
+    free(taps);
     if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw, sizeof(float) * 2 * ntw, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);
     free(tw);
