@@ -618,9 +618,10 @@ def bench_precision(rf, torch, siggen, oracle, steps, warmup):
 def bench_serving(rf, torch, seconds):
     """16-stream mix (Poisson arrivals, 1.6 Gs/s offered): latency and throughput per mode."""
     from paper_1812_02200_amd import serve
-    specs, arrivals = serve.build_mix(duration_s=seconds)
+    from siggen import mix
+    specs, arrivals = mix.build_mix(duration_s=seconds)
     log("serving: %d streams, %d buffers over %.1f s" % (len(specs), len(arrivals), seconds))
-    pool = serve.make_pool()
+    pool = mix.make_pool()
     torch.cuda.synchronize()
     res = {"config": {"workload": "16 streams, N in {64,256,1024,4096}, M in {4,8}, 8 with DDC "
                                   "banks of 10-2000 tones (T=1024, D=1000), buffers 2^16..2^24, "

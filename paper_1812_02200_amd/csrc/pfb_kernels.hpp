@@ -21,9 +21,10 @@
 //    the frame's team gathers the chosen bins into consecutive columns (same
 //    arithmetic, fewer bytes written).
 //  * LDS holds the frames of one phase, indexed with one float2 of padding per
-//    64 entries (i + 4*(i>>6)) so the strided stores of the Ns = 4 pass hit
-//    distinct banks.  Pass twiddles are staged in LDS as [r][k] tables so that
-//    lanes with consecutive k read consecutive entries.
+//    32 entries (i + (i>>5)): the FIR's radix-4 outputs, four consecutive
+//    entries per lane (lanes 32 bytes apart), and the strided stores of the
+//    Stockham passes then hit distinct banks.  Pass twiddles are staged in LDS
+//    as [r][k] tables so that lanes with consecutive k read consecutive entries.
 //  * Work-groups whose every input block lies inside the new buffer (all but
 //    the first and last few) take a branch-free path with a per-run base
 //    pointer; the others resolve each block against the retained history.
@@ -52,7 +53,7 @@ struct PfbPlan {
     static constexpr int NLG = WG / L;               // lane groups per work-group
     static constexpr int FB = NLG * 4;               // frames per phase buffer
     static constexpr int NT = N / 16;                // FFT team size (threads)
-    static constexpr int LDS = FB * N + 4 * ((FB * N) >> 6);
+    static constexpr int LDS = FB * N + ((FB * N) >> 5);
     static constexpr bool LG_IN_WAVE = L <= 64;      // FIR and FFT of an LG stay in one wave
     static constexpr bool TEAM_IN_WAVE = NT <= 64;
 };
@@ -92,7 +93,7 @@ __host__ __device__ constexpr int lds_tw_count()
     return n > 0 ? n : 1;
 }
 
-__device__ __forceinline__ int lpad(int i) { return i + 4 * (i >> 6); }
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 
 __device__ __forceinline__ void wave_fence()
 {
@@ -286,7 +287,7 @@ __device__ __forceinline__ void fir_phase(const FirState<N, M> &st, cf *lds, int
             v[k] = s;
         }
         dft4(v[0], v[1], v[2], v[3]);
-        // entries 4c .. 4c+3 never straddle a padding point (every 64)
+        // entries 4c .. 4c+3 never straddle a padding point (every 32)
         cf *dst = lds + lpad((g * 4 + qf) * N + 4 * c);
 #pragma unroll
         for (int r = 0; r < 4; ++r) dst[r] = v[r];
@@ -368,8 +369,10 @@ struct PfbShared {
 // The whole PFB computation of one logical work-group `lwg` of `G` for the
 // call described by `a`.  Shared by the single-stream kernel and the grouped
 // multi-stream kernel, so a stream's frames are computed by the same
-// instructions either way.
-template <int N, int M, int V>
+// instructions either way.  OPAQUE (callers that run the body in a loop):
+// the thread index is hidden from the optimiser, so each run's per-thread
+// addresses are computed in it instead of being kept live across runs.
+template <int N, int M, int V, bool OPAQUE = false>
 __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, PfbShared<N, V> &sh)
 {
     using P = PfbPlan<N>;
@@ -382,7 +385,11 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     cf *lds_all = sh.frames;
     cf *twl = sh.tw;
 
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    if constexpr (OPAQUE) {
+        asm volatile("" : "+v"(tid));
+        __builtin_assume(tid >= 0 && tid < P::WG);
+    }
     const cf *twg = reinterpret_cast<const cf *>(a.tw);
     for (int i = tid; i < TWL; i += P::WG) twl[i] = twg[i];
 
@@ -560,7 +567,7 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
 }
 
 template <int N, int M, int V>
-__global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_fir_fft(PfbLaunch a)
+__global__ void __launch_bounds__(PfbPlan<N>::WG) __attribute__((amdgpu_waves_per_eu(M <= 8 ? 2 : 1))) pfb_fir_fft(PfbLaunch a)
 {
     __shared__ PfbShared<N, V> sh;
     // XCD-aware work-group order: blocks are dealt round-robin to the 8 XCDs,
@@ -590,7 +597,7 @@ __global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_group(const GroupHeader *h
             else hi = mid - 1;
         }
         const PfbItem &it = items[lo];
-        pfb_body<N, M, 0>(it.a, (int)(w - it.wg_begin), it.wgs, sh);
+        pfb_body<N, M, 0, true>(it.a, (int)(w - it.wg_begin), it.wgs, sh);
         __syncthreads();   // LDS is reused by the next item
     }
 }

@@ -1219,7 +1219,7 @@ int pfb_tune(rf_pfb_t p, uint64_t nsamples, void *hip_stream, double *best_us)
     a.F = (int64_t)F;
     a.N = p->N;
     a.M = p->M;
-    static const int rls[] = {8, 12, 16, 20, 24, 32, 48, 64};
+    static const int rls[] = {8, 12, 16, 20, 24, 28, 32, 48, 64};
     // kernel variants tried: for N = 1024, M = 8 single or double-buffered
     // LDS, each with forward runs or with alternate runs walked backwards;
     // for N = 256, 512, 2048 at M = 4, 8 and N = 1024 at M = 4 the two run orders

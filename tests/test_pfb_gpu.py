@@ -217,19 +217,24 @@ def test_pfb_tune_keeps_results_bit_exact(tmp_path, monkeypatch):
     assert (tmp_path / "tune.txt").read_text().startswith("pfb gfx950 1024 8 0 %d" % n)
 
 
-@pytest.mark.parametrize("N,M,variants", [(1024, 8, (1, 16, 17)), (256, 8, (16,)), (512, 4, (16,)),
-                                          (2048, 4, (16,))])
+VARIANT_CASES = ([(1024, 8, (1, 16, 17))] +
+                 [(N, M, (16,)) for N in (256, 512, 1024, 2048) for M in (4, 8) if (N, M) != (1024, 8)])
+
+
+@pytest.mark.parametrize("N,M,variants", VARIANT_CASES)
 def test_pfb_variants_bit_exact(monkeypatch, N, M, variants):
-    """Every launch variant (LDS buffering, run direction) and run length
-    computes every frame the same way, across buffer splits that exercise the
-    history and tail paths."""
+    """Every launch variant the tuner offers (LDS buffering, run direction)
+    and run length computes every frame the same way, across buffer splits
+    that exercise the history and tail paths."""
     rf = _rf()
     import torch
     h = siggen.pfb_prototype(N, M, "kaiser")
-    n = N * 1500 + 77
+    nfr = 1500
+    n = N * nfr + 77
     iq = siggen.StreamSpec(41, siggen.pfb_small().stream.tones, 400.0).iq(0, n)
     d = to_dev(iq)
-    splits = [N * 700 + 5, N * 3 + 1, n - (N * 700 + 5) - (N * 3 + 1)]
+    cut = N * (nfr // 2 - 50) + 5
+    splits = [cut, N * 3 + 1, n - cut - (N * 3 + 1)]
     base = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), d, splits, torch)
     for var in variants:
         for rl in (8, 12, 32):
@@ -240,7 +245,7 @@ def test_pfb_variants_bit_exact(monkeypatch, N, M, variants):
             monkeypatch.delenv("RFCHAN_PFB_RUN_LEN")
             assert p.tuned_config() == (rl, var)
             got = run_pfb(p, d, splits, torch)
-            log("variant %d run length %d" % (var, rl))
+            log("N=%d M=%d variant %d run length %d" % (N, M, var, rl))
             assert np.array_equal(got.view(np.uint64), base.view(np.uint64)), (var, rl)
             # chosen channels under the same launch shape: the full spectrum's columns
             ch = np.array([5, N - 1, 0, N // 2, 77], dtype=np.int32)

@@ -59,6 +59,7 @@ def test_serve_mix_equals_alone_bit_exact(mode):
     import torch
 
     from paper_1812_02200_amd import serve
+    from siggen import mix
     specs, sizes = small_mix()
     pool_n = 1 << 20
     pool = siggen.iq_torch(siggen.StreamSpec(9, siggen.pfb_small().stream.tones, 700.0), 0, pool_n)
@@ -67,10 +68,10 @@ def test_serve_mix_equals_alone_bit_exact(mode):
     rng = np.random.default_rng(3)
     for s, sp in enumerate(specs):
         off = int(rng.integers(0, pool_n // 2))
-        mix_specs.append(serve.StreamSpecMix(sp["N"], sp["M"], sp["h"], sp["ddc"], off, 1 << 16))
+        mix_specs.append(mix.StreamSpecMix(sp["N"], sp["M"], sp["h"], sp["ddc"], off, 1 << 16))
         pos = off
         for n in sizes[s]:
-            arrivals.append(serve.Arrival(0.0, s, n, pos))
+            arrivals.append(mix.Arrival(0.0, s, n, pos))
             pos += n
     m = {"sequential": rf.RFS_MODE_SEQUENTIAL, "batched": rf.RFS_MODE_BATCHED, "graph": rf.RFS_MODE_GRAPH}[mode]
     log("serve %s: %d streams, %d requests" % (mode, len(specs), len(arrivals)))
