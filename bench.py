@@ -37,6 +37,8 @@ FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector, published (packed FP32 incl
 FP32_FMA_PEAK_TF = 78.6
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_pfb_n1024_m8_ddc_1000tones.md")
+TRACE_PROFILE = os.path.join(ROOT, "profiles", "kernel_trace_pfb_n1024_m8_ddc_1000tones_bench.md")
+MFMA_PROFILE = os.path.join(ROOT, "profiles", "mfma_busy_precision_n256_m8.md")
 KERNEL_SOURCES = os.path.join(ROOT, "paper_1812_02200_amd", "csrc")
 METRIC = "sustained Msamples/s (N=1024 PFB, 1000-tone DDC) + p99 buffer latency"
 
@@ -58,8 +60,12 @@ def parse():
     ap.add_argument("--ddc-grid", type=int, default=None,
                     help="use this DDC grid instead of autotuning")
     ap.add_argument("--trace-summary", metavar="DIR",
-                    help="summarise a rocprofv3 --kernel-trace --stats run of this script (the "
-                         "library's kernels) as markdown, and exit")
+                    help="summarise a rocprofv3 --kernel-trace run of this script (the library's "
+                         "kernels) as markdown, and exit")
+    ap.add_argument("--bench-out", metavar="FILE",
+                    help="with --trace-summary: the profiled run's own output (its JSON line)")
+    ap.add_argument("--mfma-summary", metavar="DIR",
+                    help="summarise a rocprofv3 --pmc run (MFMA counters) of --workload precision, and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_FETCH_DIR",
                                                        "PROBE_WRITE_DIR"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script "
@@ -97,6 +103,31 @@ def profiled_traffic(kernel):
     return None
 
 
+def _profile_json(path, tag):
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith(tag):
+                    rec = json.loads(line[len(tag):])
+                    return rec if rec.get("sources_sha256") == sources_digest() else None
+    except OSError:
+        return None
+    return None
+
+
+def profiled_trace(kernel):
+    """The committed kernel trace's record of the timed launches of `kernel`
+    (average duration in that profiled run, and that run's own event timing),
+    or None when there is none or the kernel sources changed since."""
+    rec = _profile_json(TRACE_PROFILE, "trace-json: ")
+    return None if rec is None else rec.get("kernels", {}).get(kernel)
+
+
+def profiled_mfma():
+    rec = _profile_json(MFMA_PROFILE, "mfma-json: ")
+    return None if rec is None else rec.get("kernels")
+
+
 SHAPES = {}                    # launch shapes given on the command line (no autotuning)
 
 COPY_PROBE_ELEMS = 1 << 26     # int32 elements per probe copy: 256 MiB read, 256 MiB written
@@ -132,18 +163,116 @@ def _per_dispatch(rows, match):
     return out
 
 
-def trace_summary(d):
+def _trace_rows(d):
     rows = []
-    for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
         with open(f) as fh:
-            rows += [r for r in csv.DictReader(fh) if "rfk::" in r["Name"]]
-    print("| kernel | calls | average us | min us | max us | share of GPU time |")
+            rows += [r for r in csv.DictReader(fh) if "rfk::" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    return rows
+
+
+def _bench_line(path):
+    """The JSON line a profiled bench.py run printed (its own event timing)."""
+    if not path:
+        return None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"metric"' in line:
+                return json.loads(line)
+    return None
+
+
+def trace_summary(d, bench_out=None):
+    """Markdown summary of a rocprofv3 --kernel-trace run of this script, plus a
+    trace-json line: for the PFB and DDC legs, the average duration of exactly
+    the timed launches (the last steps x buffers dispatches of the timed kernel
+    before the next leg's kernels), beside the same run's event timing."""
+    rows = _trace_rows(d)
+    stats = {}
+    for r in rows:
+        name = r["Kernel_Name"].replace("void ", "").split("(")[0]
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        stats.setdefault(name, []).append(dur)
+    print("| kernel | calls | average us | min us | max us |")
+    print("|---|---|---|---|---|")
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        print("| `%s` | %d | %.1f | %.1f | %.1f |" % (name, len(v), np.mean(v), min(v), max(v)))
+    line = _bench_line(bench_out)
+    rec = {"sources_sha256": sources_digest(), "kernels": {}}
+    if line:
+        for leg, key, kern_us in (("pfb", "pfb_fir_fft", (line.get("pfb") or {}).get("kernel_us")),
+                                  ("ddc", "ddc_bank", (line.get("ddc") or {}).get("kernel_us"))):
+            leg_rec = line.get(leg) if leg != "pfb" else line.get("pfb")
+            if not leg_rec or kern_us is None:
+                continue
+            n_timed = int(line["steps"]) * (16 if leg == "pfb" else 16)
+            shape = leg_rec.get("tuned", {})
+            # the timed kernel: the most frequent instance of this family in
+            # the trace's longest run of back-to-back identical dispatches
+            fam = [i for i, r in enumerate(rows) if key in r["Kernel_Name"]]
+            best, cur, best_end = 0, 0, -1
+            for j, i in enumerate(fam):
+                if j and rows[i]["Kernel_Name"] == rows[fam[j - 1]]["Kernel_Name"] and \
+                        rows[i]["Grid_Size_X"] == rows[fam[j - 1]]["Grid_Size_X"] and i == fam[j - 1] + 1:
+                    cur += 1
+                else:
+                    cur = 1
+                if cur >= best:
+                    best, best_end = cur, j
+            timed = [rows[fam[j]] for j in range(best_end - n_timed + 1, best_end + 1)] if best >= n_timed else []
+            if not timed:
+                continue
+            durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in timed]
+            span = (int(timed[-1]["End_Timestamp"]) - int(timed[0]["Start_Timestamp"])) / 1e3 / len(timed)
+            rec["kernels"][key] = {"kernel": timed[0]["Kernel_Name"].replace("void ", "").split("(")[0],
+                                   "grid": int(timed[0]["Grid_Size_X"]), "timed_launches": len(timed),
+                                   "avg_us": float(np.mean(durs)), "min_us": float(min(durs)),
+                                   "max_us": float(max(durs)), "span_us_per_launch": span,
+                                   "event_us_per_launch": float(kern_us), "shape": shape}
+        rec["bench_value"] = line.get("value")
+        rec["device"] = line.get("device")
+    print()
+    for key, k in rec["kernels"].items():
+        print("Timed launches of `%s` (grid %d threads): %d, trace average %.2f us (min %.2f, max %.2f), "
+              "first start to last end %.2f us per launch; the same run's HIP-event timing %.2f us per launch."
+              % (k["kernel"], k["grid"], k["timed_launches"], k["avg_us"], k["min_us"], k["max_us"],
+                 k["span_us_per_launch"], k["event_us_per_launch"]))
+    print()
+    print("trace-json: " + json.dumps(rec))
+
+
+def mfma_summary(d):
+    """MFMA activity of the precision leg's kernels from a rocprofv3 --pmc run
+    (SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE, SQ_INSTS_VALU_MFMA_MOPS_F16 /
+    _BF16): busy fraction = busy cycles summed over the SIMDs / (cycles of
+    one XCD x SIMDs), GRBM_GUI_ACTIVE being summed over the 8 XCDs."""
+    rows = _pmc_rows(d)
+    per = {}
+    for r in rows:
+        if "mfma" not in r["Kernel_Name"]:
+            continue
+        k = (r["Kernel_Name"].replace("void ", "").split("(")[0], r["Dispatch_Id"])
+        per.setdefault(k, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    by_kernel = {}
+    for (name, _), c in per.items():
+        by_kernel.setdefault(name, []).append(c)
+    simds = 256 * 4
+    rec = {"sources_sha256": sources_digest(), "kernels": {}}
+    print("| kernel | dispatches | MFMA busy cycles (sum of SIMDs) | GPU cycles per XCD | MFMA busy fraction | MFMA ops (MOPS counter) |")
     print("|---|---|---|---|---|---|")
-    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        name = r["Name"].replace("void ", "").split("(")[0]
-        print("| `%s` | %s | %.1f | %.1f | %.1f | %s%% |" % (
-            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-            float(r["MaxNs"]) / 1e3, r["Percentage"]))
+    for name, cs in sorted(by_kernel.items()):
+        busy = np.median([c.get("SQ_VALU_MFMA_BUSY_CYCLES", np.nan) for c in cs])
+        gui = np.median([c.get("GRBM_GUI_ACTIVE", np.nan) for c in cs]) / 8.0
+        mops = np.median([c.get("SQ_INSTS_VALU_MFMA_MOPS_F16", 0.0) + c.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0)
+                          for c in cs])
+        frac = busy / (gui * simds) if gui > 0 else float("nan")
+        rec["kernels"][name] = {"dispatches": len(cs), "mfma_busy_cycles": busy, "cycles_per_xcd": gui,
+                                "mfma_busy_frac": frac, "mfma_mops": mops}
+        print("| `%s` | %d | %.4g | %.4g | %.3f | %.4g |" % (name, len(cs), busy, gui, frac, mops))
+    print()
+    print("mfma-json: " + json.dumps(rec))
 
 
 def pmc_summary(fetch_dir, write_dir, pf_dir, pw_dir):
@@ -270,6 +399,7 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
         "tuned": {"run_len": tuned[1], "variant": tuned[2], "us_per_launch": tuned[0]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("pfb_fir_fft"),
+                     "trace": _trace_frac("pfb_fir_fft", bytes_per_launch, HBM_PEAK_GBS * 1e9),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "copy-probe scaled)",
                      "per_launch": "12 B x 2^24 samples = %.1f MB" % (bytes_per_launch / 1e6)},
@@ -277,6 +407,18 @@ def bench_pfb(rf, torch, siggen, steps, warmup):
                    "N": w.N, "M": w.M, "buffer_samples": w.buffer, "samples_per_step": w.nsamples},
     }
     return res, (w, d)
+
+
+def _trace_frac(kernel, units_per_launch, peak_per_s):
+    """The committed kernel trace of the timed launches (a profiled run of this
+    script on an earlier box): its average duration, the roofline fraction it
+    gives, and that run's own event timing; None if the sources changed."""
+    t = profiled_trace(kernel)
+    if not t:
+        return None
+    return {"avg_us": t["avg_us"], "frac": units_per_launch / (t["avg_us"] * 1e-6) / peak_per_s,
+            "event_us_same_run": t["event_us_per_launch"], "launches": t["timed_launches"],
+            "source": os.path.relpath(TRACE_PROFILE, ROOT)}
 
 
 def cpu_pfb(oracle, w, d, budget_s):
@@ -377,6 +519,7 @@ def bench_ddc(rf, torch, siggen, steps, warmup):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_FMA_PEAK_TF,
                      "unit": "TFLOP/s", "frac": achieved / FP32_FMA_PEAK_TF,
                      "traffic": profiled_traffic("ddc_bank"),
+                     "trace": _trace_frac("ddc_bank", flop, FP32_FMA_PEAK_TF * 1e12),
                      "traffic_unit": "HBM bytes per launch",
                      "valu_issue_frac": valu / VALU_ISSUE_PEAK,
                      "per_launch": "8 flop x 1024 taps x 1000 tones x %.1f outputs" % (outs / launches)},
@@ -607,6 +750,12 @@ def bench_precision(rf, torch, siggen, oracle, steps, warmup):
             flop = 2.0 * 2 * 3 * 32 * 32 * 16 * nf    # 2 GEMM stages x 3 hi/lo terms per frame
             r["mfma_tflops"] = flop / (ms / 1e3) / 1e12
             r["mfma_frac"] = r["mfma_tflops"] / MFMA_PEAK_TF
+            prof = profiled_mfma()
+            if prof:
+                for kname, kr in prof.items():
+                    if ("RF_PREC_BF16" in kname or ", 2>" in kname) == (mode == 2):
+                        r["mfma_busy_counter"] = {"kernel": kname, "busy_frac": kr["mfma_busy_frac"],
+                                                  "source": os.path.relpath(MFMA_PROFILE, ROOT)}
         res[name] = r
         log("precision %s: %.3f ms, SNR min %.1f dB" % (name, ms, ch.min()))
         p.close()
@@ -671,7 +820,10 @@ def main():
         pmc_summary(*a.pmc_summary)
         return
     if a.trace_summary:
-        trace_summary(a.trace_summary)
+        trace_summary(a.trace_summary, a.bench_out)
+        return
+    if a.mfma_summary:
+        mfma_summary(a.mfma_summary)
         return
     if a.pfb_shape:
         SHAPES["pfb"] = a.pfb_shape

@@ -38,7 +38,7 @@ constexpr int kDdcLds = 4 * kUChunk + kPairs;    // float2 entries: 160 KiB
 
 __device__ __forceinline__ uint32_t dvload(const VStream &vs, int64_t v)
 {
-    return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
+    return v < vs.H ? gptr(vs.hist)[v] : gptr(vs.in)[v - vs.H];
 }
 
 // m(m-1)/2 mod 2^64, exactly (the even factor is halved first).
@@ -63,11 +63,11 @@ __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o
     const bool live = t < a.ntones;
     uint64_t inc = 0, ph = 0, K = 0;
     if (live) {
-        inc = a.inc[t];
+        inc = gptr(a.inc)[t];
         const uint64_t m0 = a.base_abs + (uint64_t)v0;
-        ph = a.phi0[t] + m0 * inc;
+        ph = gptr(a.phi0)[t] + m0 * inc;
         if constexpr (CHIRP) {
-            K = a.chirp[t];
+            K = gptr(a.chirp)[t];
             ph += K * tri64(m0);
             inc += K * m0;      // the phase step from sample m0 to m0+1
         }
@@ -81,7 +81,7 @@ __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o
         __syncthreads();  // previous readers are done with the copies (and the table is loaded)
         for (int j = tid; j < len; j += WG) {
             const uint32_t w = dvload(vs, v0 + c0 + j);
-            const float h = a.wrev[c0 + j];
+            const float h = gptr(a.wrev)[c0 + j];
             const float ux = h * (float)(int16_t)(w & 0xffffu), uy = h * (float)(int16_t)(w >> 16);
             float4 *d = reinterpret_cast<float4 *>(lds + 4 * j);
             d[0] = make_float4(ux, uy, uy, -ux);    // U_0 = u, U_1 = -j u
@@ -130,9 +130,10 @@ __device__ __forceinline__ float2 ddc_unit(const DdcLaunch &a, int tc, int64_t o
 
 // Up to kRun consecutive outputs o .. o+cnt-1 of tone chunk tc, kept in
 // registers and stored together: a tone's row segment leaves as back-to-back
-// stores, so its cache lines are complete before they are written back (one
-// 8-byte store per output would reach HBM as partial-line writes).
-constexpr int kRun = 8;
+// stores, 16 complex values = one whole 128-byte line when the row is aligned,
+// so lines are complete before they are written back (one 8-byte store per
+// output would reach HBM as partial-line writes).
+constexpr int kRun = 16;
 template <int WG, bool CHIRP>
 __device__ __forceinline__ void ddc_run(const DdcLaunch &a, int tc, int64_t o, int cnt, float2 *lds)
 {
@@ -142,10 +143,11 @@ __device__ __forceinline__ void ddc_run(const DdcLaunch &a, int tc, int64_t o, i
         if (r < cnt) res[r] = ddc_unit<WG, CHIRP>(a, tc, o + r, lds);
     const int t = tc * WG + (int)threadIdx.x;
     if (t < a.ntones) {
-        float2 *dst = reinterpret_cast<float2 *>(a.out) + (t * a.ld + o);
+        typedef float v2 __attribute__((ext_vector_type(2)));
+        RF_GLOBAL v2 *dst = reinterpret_cast<RF_GLOBAL v2 *>(gptr(a.out)) + (t * a.ld + o);
 #pragma unroll
         for (int r = 0; r < kRun; ++r)
-            if (r < cnt) dst[r] = res[r];
+            if (r < cnt) dst[r] = v2{res[r].x, res[r].y};
     }
 }
 
@@ -157,16 +159,17 @@ __device__ __forceinline__ void ddc_tail(const DdcLaunch &a, int lwg, int G)
     const int tid = threadIdx.x;
     if (lwg == 0)
         for (int t = tid; t < a.ntones; t += WG)
-            a.phase_out[t] = a.phi0[t] + a.phase_at * a.inc[t] + (a.chirp ? a.chirp[t] * tri64(a.phase_at) : 0);
+            gptr(a.phase_out)[t] = gptr(a.phi0)[t] + a.phase_at * gptr(a.inc)[t] + (a.chirp ? gptr(a.chirp)[t] * tri64(a.phase_at) : 0);
     for (int64_t i = (int64_t)lwg * WG + tid; i < a.keep_len; i += (int64_t)G * WG)
-        a.hist_out[i] = dvload(a.vs, a.keep_from + i);
+        gptr(a.hist_out)[i] = dvload(a.vs, a.keep_from + i);
 }
 
 template <int WG>
 __device__ __forceinline__ void load_table(const float *src, float2 *lds)
 {
-    const float4 *s4 = reinterpret_cast<const float4 *>(src);
-    float4 *d4 = reinterpret_cast<float4 *>(lds + 4 * kUChunk);
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const RF_GLOBAL v4 *s4 = reinterpret_cast<const RF_GLOBAL v4 *>(gptr(src));
+    v4 *d4 = reinterpret_cast<v4 *>(lds + 4 * kUChunk);
     for (int i = threadIdx.x; i < kSinTabLen / 4; i += WG) d4[i] = s4[i];
 }
 

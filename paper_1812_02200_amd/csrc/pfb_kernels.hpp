@@ -8,21 +8,25 @@
 // window in registers and runs the FFT through LDS, writing only the spectra.
 //
 // Work decomposition (all compile-time in N):
-//  * A lane group (LG) of L = N/4 threads walks a contiguous run of frames.
-//    Thread c of an LG owns the four columns n = c + k*L (k = 0..3), holds their
-//    M taps and a window of M+3 blocks of input in registers, and produces four
-//    frames per phase.  Its four FIR outputs are exactly the inputs of one
-//    radix-4 butterfly of the first Stockham pass (stride N/4, no twiddles),
-//    which it computes before writing to LDS.
+//  * A lane group (LG) of L = N/C threads walks a contiguous run of frames
+//    (C = 4 columns per thread; 8 for N = 4096, whose lane group is then a
+//    512-thread work-group with 256 registers per thread instead of a
+//    1024-thread one with 128).  Thread c of an LG owns the C columns
+//    n = c + k*L (k < C), holds their M taps and a window of M+3 blocks of
+//    input in registers, and produces four frames per phase.  Its C FIR
+//    outputs are exactly the inputs of one radix-C butterfly of the first
+//    Stockham pass (stride N/C, no twiddles), which it computes before
+//    writing to LDS.
 //  * The remaining passes are radix-16 (radix 8/4/2 for the last one) Stockham
-//    passes: a team of N/16 threads owns one frame, every thread holds 16 points
-//    per pass.  The last pass writes the natural-order spectrum straight to HBM
+//    passes: a team of N/16 threads owns one frame, every thread holds 16
+//    points (or more, in several butterflies) per pass.  With C = 8 a phase
+//    has two frames, so the 512 threads are again one team per frame.  The last pass writes the natural-order spectrum straight to HBM
 //    -- or, when the caller chose a set of channels, back to LDS, from where
 //    the frame's team gathers the chosen bins into consecutive columns (same
 //    arithmetic, fewer bytes written).
 //  * LDS holds the frames of one phase, indexed with one float2 of padding per
-//    32 entries (i + (i>>5)): the FIR's radix-4 outputs, four consecutive
-//    entries per lane (lanes 32 bytes apart), and the strided stores of the
+//    32 entries (i + (i>>5)): the FIR's radix-C outputs, C consecutive
+//    entries per lane (lanes 8C bytes apart), and the strided stores of the
 //    Stockham passes then hit distinct banks.  Pass twiddles are staged in LDS
 //    as [r][k] tables so that lanes with consecutive k read consecutive entries.
 //  * Work-groups whose every input block lies inside the new buffer (all but
@@ -45,14 +49,26 @@
 namespace rfk {
 
 typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Threads that transform one frame in the LDS passes.
+__host__ __device__ constexpr int pfb_fft_team(int N) { return N / 16; }
+
+// Frames a lane group produces per phase: 4, or 2 with eight columns per
+// thread (the window of M+FP-1 blocks and the FIR's sums then fit in the
+// register budget at M = 8).
+__host__ __device__ constexpr int pfb_frames_per_phase(int N) { return pfb_fir_radix(N) == 8 ? 2 : 4; }
 
 template <int N>
 struct PfbPlan {
-    static constexpr int L = N / 4;                  // threads per lane group
+    static constexpr int C = pfb_fir_radix(N);      // columns per thread
+    static constexpr int L = N / C;                  // threads per lane group
     static constexpr int WG = L > 256 ? L : 256;     // threads per work-group
     static constexpr int NLG = WG / L;               // lane groups per work-group
-    static constexpr int FB = NLG * 4;               // frames per phase buffer
-    static constexpr int NT = N / 16;                // FFT team size (threads)
+    static constexpr int FP = pfb_frames_per_phase(N);   // frames per lane group and phase
+    static constexpr int FB = NLG * FP;              // frames per phase buffer
+    static constexpr int NT = pfb_fft_team(N);       // FFT team size (threads)
+    static_assert(NT * FB == WG, "one team per frame of the phase buffer");
     static constexpr int LDS = FB * N + ((FB * N) >> 5);
     static constexpr bool LG_IN_WAVE = L <= 64;      // FIR and FFT of an LG stay in one wave
     static constexpr bool TEAM_IN_WAVE = NT <= 64;
@@ -60,40 +76,54 @@ struct PfbPlan {
 
 __host__ __device__ constexpr int pass_radix(int N, int NS) { return (N / NS) >= 16 ? 16 : (N / NS); }
 
+// Pass twiddles, all staged in LDS.  Every pass but one has its full [r][k]
+// table, W_{NS R}^{k r}.  The radix-2 last pass of N = 4096 would need 2048
+// entries more than LDS holds; its butterfly j = tl + b*NT (k = j) takes
+// W_N^j = W_N^tl * W_N^(b NT), from two factor tables of NT and N/(2 NT)
+// entries.
+template <int N, int NS>
+struct TwPlace {
+    static constexpr int R = pass_radix(N, NS);
+    static constexpr bool FULL = (R == 16) || (N <= 2048);
+};
+
+// Table entries (float pairs) of the pass with stride ns.
+__host__ __device__ constexpr int pass_tw_count(int N, int ns)
+{
+    const int R = pass_radix(N, ns);
+    if (R == 16 || N <= 2048) return ns * R;
+    const int nt = pfb_fft_team(N);
+    return nt + (N / R) / nt;
+}
+
 // Offset (in float pairs) of the twiddle table of the pass with stride NS.
 __host__ __device__ constexpr int tw_offset(int N, int NS)
 {
     int off = 0;
-    for (int ns = 4; ns < NS;) {
-        int R = pass_radix(N, ns);
-        off += ns * R;
-        ns *= R;
-    }
+    for (int ns = pfb_fir_radix(N); ns < NS; ns *= pass_radix(N, ns)) off += pass_tw_count(N, ns);
     return off;
 }
-
-// Twiddles of R = 16 passes, and of every pass when N <= 2048, are staged in
-// LDS; otherwise (the radix-4 last pass of N = 4096) W^k is read once and its
-// powers formed by multiplication.
-template <int N, int NS>
-struct TwPlace {
-    static constexpr int R = pass_radix(N, NS);
-    static constexpr bool IN_LDS = (R == 16) || (N <= 2048);
-};
 
 template <int N>
 __host__ __device__ constexpr int lds_tw_count()
 {
-    int n = 0;
-    for (int ns = 4; ns < N;) {
-        int R = pass_radix(N, ns);
-        if (R == 16 || N <= 2048) n += ns * R;
-        ns *= R;
-    }
+    const int n = tw_offset(N, N);
     return n > 0 ? n : 1;
 }
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+
+// The value, hidden from the optimiser when ON: addresses derived from it
+// inside a loop are then formed where they are used instead of being hoisted
+// out of the loop and held (or spilled) across it.  (An index, not a
+// pointer: a laundered pointer loses its address space and its loads become
+// flat loads, which LDS waits then also wait for.)
+template <bool ON, typename T>
+__device__ __forceinline__ T phase_local(T x)
+{
+    if constexpr (ON) asm volatile("" : "+v"(x));
+    return x;
+}
 
 __device__ __forceinline__ void wave_fence()
 {
@@ -113,7 +143,7 @@ __device__ __forceinline__ void group_sync()
 
 __device__ __forceinline__ uint32_t vload(const VStream &vs, int64_t v)
 {
-    return v < vs.H ? vs.hist[v] : vs.in[v - vs.H];
+    return v < vs.H ? gptr(vs.hist)[v] : gptr(vs.in)[v - vs.H];
 }
 
 __device__ __forceinline__ cf unpack(uint32_t w)
@@ -121,30 +151,31 @@ __device__ __forceinline__ cf unpack(uint32_t w)
     return {(float)(int16_t)(w & 0xffffu), (float)(int16_t)(w >> 16)};
 }
 
-// Load four columns c + k*L of virtual block b (samples [bN, bN+N)), resolving
-// each against history, new input and end of data.
+// Load the C columns c + k*L of virtual block b (samples [bN, bN+N)),
+// resolving each against history, new input and end of data.
 template <int N>
 __device__ __forceinline__ void load_block(const VStream &vs, int64_t vlen, int64_t b, int c,
-                                           uint32_t (&w)[4])
+                                           uint32_t (&w)[pfb_fir_radix(N)])
 {
-    constexpr int L = N / 4;
+    constexpr int C = pfb_fir_radix(N);
+    constexpr int L = N / C;
     const int64_t base = b * N;
     if (base + N <= vlen) {
         if (base >= vs.H) {
-            const uint32_t *p = vs.in + (base - vs.H) + c;
+            const RF_GLOBAL uint32_t *p = gptr(vs.in) + (base - vs.H) + c;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = p[k * L];
+            for (int k = 0; k < C; ++k) w[k] = p[k * L];
         } else if (base + N <= vs.H) {
-            const uint32_t *p = vs.hist + base + c;
+            const RF_GLOBAL uint32_t *p = gptr(vs.hist) + base + c;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = p[k * L];
+            for (int k = 0; k < C; ++k) w[k] = p[k * L];
         } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = vload(vs, base + c + k * L);
+            for (int k = 0; k < C; ++k) w[k] = vload(vs, base + c + k * L);
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < C; ++k) {
             int64_t v = base + c + k * L;
             w[k] = v < vlen ? vload(vs, v) : 0u;
         }
@@ -156,9 +187,8 @@ __device__ __forceinline__ void load_block(const VStream &vs, int64_t vlen, int6
 // j = tl + b*NT.  The last pass stores to `outf` (global, frame base), or,
 // with SEL (chosen channels), back to LDS in natural bin order.
 template <int N, int R, int NS, bool LAST, bool NT_STORE, bool SEL>
-__device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
-                                         const cf *__restrict__ twg, float *__restrict__ outf,
-                                         bool valid, const int32_t *__restrict__ sel)
+__device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl, RF_GLOBAL float *__restrict__ outf,
+                                         bool valid, const RF_GLOBAL int32_t *__restrict__ sel)
 {
     constexpr int NT = PfbPlan<N>::NT;
     constexpr int NB = N / R;
@@ -179,17 +209,12 @@ __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
         const int j = tl + b * NT;
         const int k = j % NS;
         if constexpr (NS > 1) {
-            if constexpr (TwPlace<N, NS>::IN_LDS) {
+            if constexpr (TwPlace<N, NS>::FULL) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], twl[TOFF + r * NS + k]);
             } else {
-                const cf w1 = twg[TOFF + NS + k];
-                cf w = w1;
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    v[b][r] = cmul(v[b][r], w);
-                    if (r + 1 < R) w = cmul(w, w1);
-                }
+                static_assert(R == 2 && NS * R == N, "factor tables serve the radix-2 last pass");
+                v[b][1] = cmul(v[b][1], cmul(twl[TOFF + tl], twl[TOFF + NT + b]));
             }
         }
         dft<R>(v[b]);
@@ -199,7 +224,7 @@ __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     f2v o = {v[b][r].x, v[b][r].y};
-                    f2v *dst = (f2v *)(outf + 2 * (idxD + r * NS));
+                    RF_GLOBAL f2v *dst = (RF_GLOBAL f2v *)(outf + 2 * (idxD + r * NS));
                     if constexpr (NT_STORE)
                         __builtin_nontemporal_store(o, dst);
                     else
@@ -217,14 +242,13 @@ __device__ __forceinline__ void fft_pass(cf *lds, int fb, int tl, const cf *twl,
 // STAGED: the last pass leaves the spectrum in LDS (natural bin order) for
 // the caller to copy out.
 template <int N, int NS, bool NT_STORE, bool SEL, bool STAGED = false>
-__device__ __forceinline__ void fft_passes(cf *lds, int fb, int tl, const cf *twl,
-                                           const cf *__restrict__ twg, float *__restrict__ outf,
-                                           bool valid, const int32_t *__restrict__ sel, int nsel)
+__device__ __forceinline__ void fft_passes(cf *lds, int fb, int tl, const cf *twl, RF_GLOBAL float *__restrict__ outf,
+                                           bool valid, const RF_GLOBAL int32_t *__restrict__ sel, int nsel)
 {
     if constexpr (NS < N) {
         constexpr int R = pass_radix(N, NS);
-        fft_pass<N, R, NS, NS * R == N, NT_STORE, SEL || STAGED>(lds, fb, tl, twl, twg, outf, valid, sel);
-        fft_passes<N, NS * R, NT_STORE, SEL, STAGED>(lds, fb, tl, twl, twg, outf, valid, sel, nsel);
+        fft_pass<N, R, NS, NS * R == N, NT_STORE, SEL || STAGED>(lds, fb, tl, twl, outf, valid, sel);
+        fft_passes<N, NS * R, NT_STORE, SEL, STAGED>(lds, fb, tl, twl, outf, valid, sel, nsel);
     } else if constexpr (SEL) {
         // the spectrum is in LDS: the team gathers the chosen bins into
         // consecutive columns (sel = the bins, in output order)
@@ -233,7 +257,7 @@ __device__ __forceinline__ void fft_passes(cf *lds, int fb, int tl, const cf *tw
             for (int c = tl; c < nsel; c += PfbPlan<N>::NT) {
                 const cf x = lds[lpad(fb + sel[c])];
                 f2v o = {x.x, x.y};
-                f2v *dst = (f2v *)(outf + 2 * c);
+                RF_GLOBAL f2v *dst = (RF_GLOBAL f2v *)(outf + 2 * c);
                 if constexpr (NT_STORE)
                     __builtin_nontemporal_store(o, dst);
                 else
@@ -260,23 +284,92 @@ struct WinT<true> {
     __device__ __forceinline__ cf get() const { return unpack(w); }
 };
 
-template <int N, int M>
-struct FirState {
-    static constexpr bool PACKED = (M > 8) || (N >= 4096);
-    static constexpr int W = M + 3;   // window blocks fp .. fp+M+2
-    float hr[M][4];
-    WinT<PACKED> xw[W][4];
+// Eight columns per thread (N = 4096): M x 8 taps would not fit beside the
+// window.  The handle stores a per-thread copy [c][m][k] (the taps of thread
+// c's columns for tap m) after the natural [m N + n] layout.  For M <= 4 each
+// thread copies its rows into LDS (64 KiB at most, read only by that thread);
+// otherwise every phase reads them from that copy, through the caches (all
+// work-groups of an XCD read the same taps).  (Measured: splitting larger M
+// between LDS and memory, or keeping some rows in registers, made the
+// compiler hoist more and ran slower.)  Every sum adds its M terms in tap
+// order either way.
+template <int N>
+struct TapsInMemory {
+    static constexpr bool ON = pfb_fir_radix(N) == 8;
 };
 
-// FIR of the phase's four frames, first radix-4 pass, store to LDS.
+template <int N, int M>
+struct TapTiers {
+    static constexpr int LR = TapsInMemory<N>::ON && M <= 4 ? M : 0;   // rows in LDS
+    static constexpr int LDS_F4 = LR * 2 * (N / 8);                  // LDS float4 entries
+};
+
+template <int N, int M>
+struct FirState {
+    static constexpr int C = pfb_fir_radix(N);
+    static constexpr bool PACKED = (M > 8) || (C == 8);
+    static constexpr int FP = pfb_frames_per_phase(N);
+    static constexpr int W = M + FP - 1;   // window blocks fp .. fp+M+FP-2
+    float hr[TapsInMemory<N>::ON ? 1 : M][C];
+    const RF_GLOBAL f4v *tp;          // TapsInMemory: this thread's [m] rows of C taps
+    const f4v *tl;                    // TapsInMemory: its LDS rows, row m at tl[2 m L]
+    WinT<PACKED> xw[W][C];
+};
+
+// FIR of the phase's FP frames, first radix-C pass, store to LDS.
 template <int N, int M>
 __device__ __forceinline__ void fir_phase(const FirState<N, M> &st, cf *lds, int g, int c)
 {
+    constexpr int C = FirState<N, M>::C;
+    constexpr int FP = FirState<N, M>::FP;
+    if constexpr (TapsInMemory<N>::ON) {
+        // taps outer: each row of C taps is read once and applied to the FP
+        // frames; every sum still adds its M terms in tap order
+        cf s[FP][C];
 #pragma unroll
-    for (int qf = 0; qf < 4; ++qf) {
-        cf v[4];
+        for (int qf = 0; qf < FP; ++qf)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < C; ++k) s[qf][k] = cf{0.f, 0.f};
+        using TT = TapTiers<N, M>;
+        constexpr int L = N / C;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            float t[C];
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                const f4v t4 = m < TT::LR ? st.tl[(m * (C / 4) + q) * L] : st.tp[m * (C / 4) + q];
+                t[4 * q] = t4.x;
+                t[4 * q + 1] = t4.y;
+                t[4 * q + 2] = t4.z;
+                t[4 * q + 3] = t4.w;
+            }
+#pragma unroll
+            for (int qf = 0; qf < FP; ++qf)
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    // each use converts afresh: converted copies kept for
+                    // the block's second use would cost two registers per word
+                    uint32_t w = st.xw[qf + m][k].w;
+                    asm volatile("" : "+v"(w));
+                    const cf x = unpack(w);
+                    s[qf][k].x = __builtin_fmaf(t[k], x.x, s[qf][k].x);
+                    s[qf][k].y = __builtin_fmaf(t[k], x.y, s[qf][k].y);
+                }
+        }
+#pragma unroll
+        for (int qf = 0; qf < FP; ++qf) {
+            dft<C>(s[qf]);
+            cf *dst = lds + lpad((g * FP + qf) * N + C * c);
+#pragma unroll
+            for (int r = 0; r < C; ++r) dst[r] = s[qf][r];
+        }
+        return;
+    }
+#pragma unroll
+    for (int qf = 0; qf < FP; ++qf) {
+        cf v[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
             cf s = {0.f, 0.f};
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -286,26 +379,29 @@ __device__ __forceinline__ void fir_phase(const FirState<N, M> &st, cf *lds, int
             }
             v[k] = s;
         }
-        dft4(v[0], v[1], v[2], v[3]);
-        // entries 4c .. 4c+3 never straddle a padding point (every 32)
-        cf *dst = lds + lpad((g * 4 + qf) * N + 4 * c);
+        dft<C>(v);
+        // entries Cc .. Cc+C-1 never straddle a padding point (every 32)
+        cf *dst = lds + lpad((g * FP + qf) * N + C * c);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[r] = v[r];
+        for (int r = 0; r < C; ++r) dst[r] = v[r];
     }
 }
 
 template <int N, int M>
-__device__ __forceinline__ void shift_window(FirState<N, M> &st, const uint32_t (&pre)[4][4])
+__device__ __forceinline__ void shift_window(FirState<N, M> &st,
+                                             const uint32_t (&pre)[pfb_frames_per_phase(N)][pfb_fir_radix(N)])
 {
     constexpr int W = FirState<N, M>::W;
+    constexpr int C = FirState<N, M>::C;
+    constexpr int FP = FirState<N, M>::FP;
 #pragma unroll
-    for (int i = 0; i + 4 < W; ++i)
+    for (int i = 0; i + FP < W; ++i)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) st.xw[i][k] = st.xw[i + 4][k];
+        for (int k = 0; k < C; ++k) st.xw[i][k] = st.xw[i + FP][k];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FP; ++i)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) st.xw[W - 4 + i][k].set(pre[i][k]);
+        for (int k = 0; k < C; ++k) st.xw[W - FP + i][k].set(pre[i][k]);
 }
 
 // Small N: a frame's team is a few threads (one for N = 16), so stores
@@ -327,6 +423,7 @@ __device__ __forceinline__ void staged_copy(const cf *lds, float *__restrict__ o
 {
     constexpr int L = PfbPlan<N>::L;
     static_assert(L <= 64 && 64 % L == 0, "lane groups inside one wave");
+    static_assert(PfbPlan<N>::FP == 4, "four frames per phase");
     constexpr int LGW = 64 / L;   // lane groups per wave
     constexpr int CH = 4 * N;     // values of a lane group's four frames
     const int tid = threadIdx.x;
@@ -342,7 +439,7 @@ __device__ __forceinline__ void staged_copy(const cf *lds, float *__restrict__ o
             if (fg + e / N < f1) {
                 const cf x = lds[lpad(4 * g * N + e)];
                 f2v o = {x.x, x.y};
-                f2v *dst = (f2v *)(out + 2 * (fg * N + e));
+                RF_GLOBAL f2v *dst = (RF_GLOBAL f2v *)(gptr(out) + 2 * (fg * N + e));
                 if constexpr (NT_STORE)
                     __builtin_nontemporal_store(o, dst);
                 else
@@ -359,11 +456,12 @@ struct PfbVariant {
     static constexpr int NBUF = DBUF ? 2 : 1;
 };
 
-// LDS of the PFB body, sized for its plan and variant.
-template <int N, int V>
+// LDS of the PFB body, sized for its plan, variant and tap count.
+template <int N, int V, int M>
 struct PfbShared {
     cf frames[PfbVariant<N, V>::NBUF * PfbPlan<N>::LDS];
     cf tw[lds_tw_count<N>()];
+    f4v taps[TapTiers<N, M>::LDS_F4 > 0 ? TapTiers<N, M>::LDS_F4 : 1];   // [m][q][c]
 };
 
 // The whole PFB computation of one logical work-group `lwg` of `G` for the
@@ -373,15 +471,24 @@ struct PfbShared {
 // the thread index is hidden from the optimiser, so each run's per-thread
 // addresses are computed in it instead of being kept live across runs.
 template <int N, int M, int V, bool OPAQUE = false>
-__device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, PfbShared<N, V> &sh)
+__device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, PfbShared<N, V, M> &sh)
 {
     using P = PfbPlan<N>;
     using VV = PfbVariant<N, V>;
     constexpr int L = P::L;
+    constexpr int C = P::C;
+    constexpr int FP = P::FP;
     constexpr int W = FirState<N, M>::W;
     constexpr int TWL = lds_tw_count<N>();
     // one barrier per phase when double buffered, else two
     constexpr bool SYNC2 = !P::LG_IN_WAVE && !VV::DBUF;
+    // eight columns per thread: the FFT's per-thread addresses (16 stores and
+    // twiddles per pass) are recomputed in each phase rather than kept live
+    constexpr bool RELOAD = C == 8;
+    // The next phase's input is requested before the FIR, except where the
+    // FIR reads its taps from memory: loads complete in order, so the tap
+    // loads would wait for the prefetch; it follows the FIR instead.
+    constexpr bool PRE_AFTER = TapsInMemory<N>::ON;
     cf *lds_all = sh.frames;
     cf *twl = sh.tw;
 
@@ -390,19 +497,22 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
         asm volatile("" : "+v"(tid));
         __builtin_assume(tid >= 0 && tid < P::WG);
     }
-    const cf *twg = reinterpret_cast<const cf *>(a.tw);
-    for (int i = tid; i < TWL; i += P::WG) twl[i] = twg[i];
+    const RF_GLOBAL f2v *twg = reinterpret_cast<const RF_GLOBAL f2v *>(gptr(a.tw));
+    for (int i = tid; i < TWL; i += P::WG) {
+        const f2v t = twg[i];
+        twl[i] = cf{t.x, t.y};
+    }
 
     const VStream vs = a.vs;
     const int64_t vlen = vs.H + vs.n;
     const int64_t F = a.F;
     const int RL = a.run_len;
-    const int nph = RL >> 2;
+    const int nph = RL / FP;
     // output row length: all N bins, or the chosen channels (variant bit 8:
     // a.sel lists the bins in output order; compiled only into that variant)
     constexpr bool SEL = (V & 8) != 0;
     constexpr bool STAGE = PfbStage<N>::ON && !SEL;
-    const int32_t *sel = SEL ? a.sel : nullptr;
+    const RF_GLOBAL int32_t *sel = SEL ? gptr(a.sel) : nullptr;
     const int64_t ldo = SEL ? (int64_t)a.nsel : (int64_t)N;
 
     const int g = tid / L;
@@ -416,15 +526,25 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     const bool fast = wg_first * N >= vs.H && (wg_last + 1) * N <= vlen;
 
     FirState<N, M> st;
+    if constexpr (TapsInMemory<N>::ON) {
+        using TT = TapTiers<N, M>;
+        st.tp = reinterpret_cast<const RF_GLOBAL f4v *>(gptr(a.taps) + (size_t)N * M) + (size_t)c * M * (C / 4);
+        st.tl = sh.taps + c;
 #pragma unroll
-    for (int m = 0; m < M; ++m)
+        for (int m = 0; m < TT::LR; ++m)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) st.hr[m][k] = a.taps[m * N + c + k * L];
+            for (int q = 0; q < C / 4; ++q) sh.taps[(m * (C / 4) + q) * L + c] = st.tp[m * (C / 4) + q];
+    } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int k = 0; k < C; ++k) st.hr[m][k] = gptr(a.taps)[m * N + c + k * L];
+    }
 
     // FFT team of this thread (may belong to another lane group for N >= 512)
     const int slot = tid / P::NT;
     const int tl = tid - slot * P::NT;
-    const int lg2 = slot >> 2, q2 = slot & 3;
+    const int lg2 = slot / FP, q2 = slot - lg2 * FP;
     const int64_t f0t = ((int64_t)lwg * P::NLG + lg2) * RL;
     const int64_t f1t = (f0t + RL < F) ? f0t + RL : F;
     __syncthreads();   // twiddle tables staged
@@ -439,29 +559,34 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             // is uniform per wave.)
             static_assert(P::L >= 64, "lane groups of whole waves");
             const bool back = (((int64_t)lwg * P::NLG + g) & 1) == 0;
-            const uint32_t *base = vs.in + (f0 * N - vs.H) + c;
-            const int64_t b0 = back ? 4 * (int64_t)(nph - 1) : 0;   // first window block
+            const RF_GLOBAL uint32_t *base = gptr(vs.in) + (f0 * N - vs.H) + c;
+            const int64_t b0 = back ? FP * (int64_t)(nph - 1) : 0;   // first window block
 #pragma unroll
             for (int i = 0; i < W; ++i)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) st.xw[i][k].set(base[(b0 + i) * N + k * L]);
+                for (int k = 0; k < C; ++k) st.xw[i][k].set(base[(b0 + i) * N + k * L]);
 #pragma unroll 1
             for (int it = 0; it < nph; ++it) {
                 const int ph = back ? nph - 1 - it : it;
                 cf *lds = lds_all + (VV::DBUF ? (it & 1) * P::LDS : 0);
-                uint32_t pre[4][4];
+                uint32_t pre[FP][C];
                 const bool more = it + 1 < nph;
-                if (more) {
-                    const uint32_t *p = base + (int64_t)(back ? 4 * ph - 4 : 4 * ph + W) * N;
+                auto prefetch = [&]() __attribute__((always_inline)) {
+                    if (more) {
+                        const RF_GLOBAL uint32_t *p = (base - c) + phase_local<RELOAD>(c) + (int64_t)(back ? FP * ph - FP : FP * ph + W) * N;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                        for (int i = 0; i < FP; ++i)
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) pre[i][k] = p[i * N + k * L];
-                }
+                            for (int k = 0; k < C; ++k) pre[i][k] = p[i * N + k * L];
+                    }
+                };
+                if constexpr (!PRE_AFTER) prefetch();
                 fir_phase<N, M>(st, lds, g, c);
+                if constexpr (PRE_AFTER) prefetch();
                 group_sync<!P::LG_IN_WAVE>();
-                fft_passes<N, 4, VV::NT_STORE, SEL, STAGE>(lds, slot * N, tl, twl, twg,
-                                                      a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, sel, a.nsel);
+                fft_passes<N, C, VV::NT_STORE, SEL, STAGE>(lds, slot * N, phase_local<RELOAD>(tl), twl,
+                                                      gptr(a.out) + 2 * (f0t + FP * ph + q2) * ldo, true, sel,
+                                                      a.nsel);
                 if constexpr (STAGE) {
                     wave_fence();
                     staged_copy<N, VV::NT_STORE>(lds, a.out, (int64_t)lwg * P::NLG, RL, ph, F);
@@ -471,13 +596,13 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
                 if (more) {
                     if (back) {
 #pragma unroll
-                        for (int i = W - 1; i >= 4; --i)
+                        for (int i = W - 1; i >= FP; --i)
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) st.xw[i][k] = st.xw[i - 4][k];
+                            for (int k = 0; k < C; ++k) st.xw[i][k] = st.xw[i - FP][k];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+                        for (int i = 0; i < FP; ++i)
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) st.xw[i][k].set(pre[i][k]);
+                            for (int k = 0; k < C; ++k) st.xw[i][k].set(pre[i][k]);
                     } else {
                         shift_window<N, M>(st, pre);
                     }
@@ -487,26 +612,30 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     }
     if (fast && (V & 16) == 0) {
         // block b of this lane group starts at in + (f0 + b)*N - H
-        const uint32_t *base = vs.in + (f0 * N - vs.H) + c;
+        const RF_GLOBAL uint32_t *base = gptr(vs.in) + (f0 * N - vs.H) + c;
 #pragma unroll
         for (int i = 0; i < W; ++i)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) st.xw[i][k].set(base[i * N + k * L]);
+            for (int k = 0; k < C; ++k) st.xw[i][k].set(base[i * N + k * L]);
         auto phase = [&](int ph) __attribute__((always_inline)) {
             cf *lds = lds_all + (VV::DBUF ? (ph & 1) * P::LDS : 0);
-            uint32_t pre[4][4];
+            uint32_t pre[FP][C];
             const bool more = ph + 1 < nph;
-            if (more) {
-                const uint32_t *p = base + (int64_t)(4 * ph + W) * N;
+            auto prefetch = [&]() __attribute__((always_inline)) {
+                if (more) {
+                    const RF_GLOBAL uint32_t *p = (base - c) + phase_local<RELOAD>(c) + (int64_t)(FP * ph + W) * N;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                    for (int i = 0; i < FP; ++i)
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) pre[i][k] = p[i * N + k * L];
-            }
+                        for (int k = 0; k < C; ++k) pre[i][k] = p[i * N + k * L];
+                }
+            };
+            if constexpr (!PRE_AFTER) prefetch();
             fir_phase<N, M>(st, lds, g, c);
+            if constexpr (PRE_AFTER) prefetch();
             group_sync<!P::LG_IN_WAVE>();
-            fft_passes<N, 4, VV::NT_STORE, SEL, STAGE>(lds, slot * N, tl, twl, twg,
-                                                  a.out + 2 * (f0t + 4 * ph + q2) * ldo, true, sel, a.nsel);
+            fft_passes<N, C, VV::NT_STORE, SEL, STAGE>(lds, slot * N, phase_local<RELOAD>(tl), twl,
+                                                  gptr(a.out) + 2 * (f0t + FP * ph + q2) * ldo, true, sel, a.nsel);
             if constexpr (STAGE) {
                 wave_fence();
                 staged_copy<N, VV::NT_STORE>(lds, a.out, (int64_t)lwg * P::NLG, RL, ph, F);
@@ -515,10 +644,10 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             else wave_fence();
             if (more) shift_window<N, M>(st, pre);
         };
-        // Three phases bring in 12 blocks; for M <= 9 that is more than the
-        // window holds, so in a group of three no window value survives to the
-        // loop edge and the window needs no register rotation there (a move
-        // per value).
+        // Three phases bring in 3 FP blocks; when that is at least the window
+        // (M <= 2 FP + 1), no window value survives to the loop edge of a
+        // group of three and the window needs no register rotation there (a
+        // move per value).
         int ph = 0;
         for (; ph + 3 <= nph; ph += 3) {
             phase(ph);
@@ -529,27 +658,31 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     } else if (!fast) {
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            uint32_t w[4];
+            uint32_t w[C];
             load_block<N>(vs, vlen, f0 + i, c, w);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) st.xw[i][k].set(w[k]);
+            for (int k = 0; k < C; ++k) st.xw[i][k].set(w[k]);
         }
         for (int ph = 0; ph < nph; ++ph) {
             cf *lds = lds_all + (VV::DBUF ? (ph & 1) * P::LDS : 0);
-            const int64_t fp = f0 + 4 * ph;
-            uint32_t pre[4][4];
-            const bool more = (ph + 1 < nph) && (fp + 4 < F);
-            if (more) {
+            const int64_t fp = f0 + FP * ph;
+            uint32_t pre[FP][C];
+            const bool more = (ph + 1 < nph) && (fp + FP < F);
+            auto prefetch = [&]() __attribute__((always_inline)) {
+                if (more) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) load_block<N>(vs, vlen, fp + W + i, c, pre[i]);
-            }
+                    for (int i = 0; i < FP; ++i) load_block<N>(vs, vlen, fp + W + i, c, pre[i]);
+                }
+            };
+            if constexpr (!PRE_AFTER) prefetch();
             if (fp < F) fir_phase<N, M>(st, lds, g, c);
+            if constexpr (PRE_AFTER) prefetch();
             group_sync<!P::LG_IN_WAVE>();
             {
-                const int64_t f = f0t + 4 * ph + q2;
+                const int64_t f = f0t + FP * ph + q2;
                 const bool valid = f < f1t;
-                fft_passes<N, 4, VV::NT_STORE, SEL, STAGE>(lds, slot * N, tl, twl, twg,
-                                                      a.out + 2 * (valid ? f : 0) * ldo, valid, sel, a.nsel);
+                fft_passes<N, C, VV::NT_STORE, SEL, STAGE>(lds, slot * N, phase_local<RELOAD>(tl), twl,
+                                                      gptr(a.out) + 2 * (valid ? f : 0) * ldo, valid, sel, a.nsel);
             }
             if constexpr (STAGE) {
                 wave_fence();
@@ -563,13 +696,13 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
 
     // retained history for the next call (sources are read-only this call)
     for (int64_t i = (int64_t)lwg * P::WG + tid; i < a.keep_len; i += (int64_t)G * P::WG)
-        a.hist_out[i] = vload(vs, a.keep_from + i);
+        gptr(a.hist_out)[i] = vload(vs, a.keep_from + i);
 }
 
 template <int N, int M, int V>
 __global__ void __launch_bounds__(PfbPlan<N>::WG) __attribute__((amdgpu_waves_per_eu(M <= 8 ? 2 : 1))) pfb_fir_fft(PfbLaunch a)
 {
-    __shared__ PfbShared<N, V> sh;
+    __shared__ PfbShared<N, V, M> sh;
     // XCD-aware work-group order: blocks are dealt round-robin to the 8 XCDs,
     // so give XCD x the contiguous logical range [x*q + min(x,r), ...).
     const int G = gridDim.x, bid = blockIdx.x;
@@ -584,9 +717,10 @@ __global__ void __launch_bounds__(PfbPlan<N>::WG) __attribute__((amdgpu_waves_pe
 // output.  The item table lives in device memory and is rewritten between
 // launches, so one captured graph serves every batch.
 template <int N, int M>
-__global__ void __launch_bounds__(PfbPlan<N>::WG) pfb_group(const GroupHeader *hdr, const PfbItem *items)
+__global__ void __launch_bounds__(PfbPlan<N>::WG) __attribute__((amdgpu_waves_per_eu(M <= 8 ? 2 : 1)))
+pfb_group(const GroupHeader *hdr, const PfbItem *items)
 {
-    __shared__ PfbShared<N, 0> sh;
+    __shared__ PfbShared<N, 0, M> sh;
     const int nitems = hdr->count;
     const int64_t total = hdr->total;
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {

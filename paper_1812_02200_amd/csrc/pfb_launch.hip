@@ -8,44 +8,46 @@ namespace rfk {
 
 int pfb_twiddle_count(int N)
 {
-    int n = 0;
-    for (int ns = 4; ns < N;) {
-        int R = pass_radix(N, ns);
-        n += ns * R;
-        ns *= R;
-    }
+    const int n = tw_offset(N, N);
     return n > 0 ? n : 1;
 }
 
 // Table of the pass with stride ns and radix R, at offset tw_offset(N, ns):
-// entry [r][k] = exp(-2 pi i k r / (ns R)), computed in FP64, rounded to FP32.
+// entry [r][k] = exp(-2 pi i k r / (ns R)); for the radix-2 last pass of
+// N = 4096, the factors exp(-2 pi i t / N), t < NT, then exp(-2 pi i b NT / N),
+// b < N/(2 NT).  Computed in FP64, rounded to FP32.
 void pfb_twiddle_fill(int N, float *tw)
 {
     const double two_pi = 6.283185307179586476925286766559;
-    int off = 0;
+    auto put = [&](int i, long e, long period) {
+        const double ang = -two_pi * (double)(e % period) / (double)period;
+        tw[2 * i] = (float)cos(ang);
+        tw[2 * i + 1] = (float)sin(ang);
+    };
     tw[0] = 1.f;
     tw[1] = 0.f;
-    for (int ns = 4; ns < N;) {
-        int R = pass_radix(N, ns);
-        for (int k = 0; k < ns; ++k)
-            for (int r = 0; r < R; ++r) {
-                long e = ((long)k * r) % ((long)ns * R);
-                double ang = -two_pi * (double)e / (double)(ns * R);
-                tw[2 * (off + r * ns + k)] = (float)cos(ang);
-                tw[2 * (off + r * ns + k) + 1] = (float)sin(ang);
-            }
-        off += ns * R;
-        ns *= R;
+    for (int ns = pfb_fir_radix(N); ns < N; ns *= pass_radix(N, ns)) {
+        const int R = pass_radix(N, ns), off = tw_offset(N, ns);
+        if (R == 16 || N <= 2048) {
+            for (int k = 0; k < ns; ++k)
+                for (int r = 0; r < R; ++r) put(off + r * ns + k, (long)k * r, (long)ns * R);
+        } else {
+            const int nt = pfb_fft_team(N), nb = (N / R) / nt;
+            for (int t = 0; t < nt; ++t) put(off + t, t, N);
+            for (int b = 0; b < nb; ++b) put(off + nt + b, (long)b * nt, N);
+        }
     }
 }
 
 int pfb_default_run_len(int N, int M, int64_t F)
 {
     (void)M;
-    // Aim for at least 512 work-groups (two per CU), runs of 8 to 64 frames;
-    // a work-group holds max(1, 1024 / N) lane groups, each walking one run.
+    // Aim for one round of work-groups at 512 threads per CU (two 256-thread
+    // work-groups per CU up to N = 1024, one 512-thread work-group from
+    // N = 2048), runs of 8 to 64 frames; a work-group holds max(1, 1024 / N)
+    // lane groups, each walking one run.
     const int64_t nlg = N >= 1024 ? 1 : 1024 / N;
-    const int64_t target = 512 * nlg;
+    const int64_t target = (N >= 2048 ? 256 : 512) * nlg;
     int64_t rl = (F + target - 1) / target;
     if (rl < 8) rl = 8;
     if (rl > 64) rl = 64;

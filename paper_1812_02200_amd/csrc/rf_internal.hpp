@@ -62,6 +62,18 @@ struct GroupHeader {
     int64_t total;          // logical work-groups (PFB) or work units (DDC)
 };
 
+// A pointer loaded from device memory (an item table of a grouped launch)
+// carries no address space, so accesses through it compile to flat
+// instructions, which every LDS wait then also waits for.  Hot accesses go
+// through a pointer typed in the global address space instead (a no-op
+// where the compiler already knows it, as for kernel arguments).
+#define RF_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ RF_GLOBAL T *gptr(T *p)
+{
+    return (RF_GLOBAL T *)p;
+}
+
 struct PfbItem {
     PfbLaunch a;
     int64_t wg_begin;       // first logical work-group of this item
@@ -77,6 +89,11 @@ int pfb_group_wg_size(int N);
 
 // Fill n packed I/Q words with pseudo-random 14-bit values (tuning scratch).
 hipError_t fill_iq(uint32_t *p, uint64_t n, hipStream_t s);
+
+// Columns per thread in the fused PFB kernel, which is also the radix of the
+// FFT pass done in the FIR's registers: 8 for N = 4096 (512-thread
+// work-groups, so each thread keeps a 256-register budget), else 4.
+__host__ __device__ constexpr int pfb_fir_radix(int N) { return N >= 4096 ? 8 : 4; }
 
 // Twiddle table size (float pairs) for an N-point plan.
 int pfb_twiddle_count(int N);

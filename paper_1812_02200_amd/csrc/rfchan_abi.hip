@@ -244,7 +244,8 @@ size_t pfb_footprint(int N, int M, int mode)
     const size_t span = (size_t)N * M;
     const size_t tw = mode == RF_DFT_FFT_F32 ? (size_t)rfk::pfb_twiddle_count(N) * 8
                                              : (size_t)rfk::pfb_mfma_table_floats() * 4;
-    return span * 4 /* taps */ + tw + 2 * span * 4 /* history */;
+    const size_t taps = (rfk::pfb_fir_radix(N) == 8 && mode == RF_DFT_FFT_F32 ? 2 : 1) * span * 4;
+    return taps + tw + 2 * span * 4 /* history */;
 }
 
 }  // namespace rfi
@@ -351,7 +352,12 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         pfb_free(p);
         return fail(RF_ENOMEM, "pfb_create: host allocation");
     }
-    float *taps = (float *)malloc(sizeof(float) * span);
+    // Eight columns per thread (N = 4096): the natural layout is followed by a
+    // per-thread copy [c][m][k] = h[m N + c + k N/8] that the kernel reads a
+    // row of eight taps at a time
+    const int fir_c = rfk::pfb_fir_radix(nchan);
+    const size_t ntaps_dev = fir_c == 8 && dft_mode == RF_DFT_FFT_F32 ? 2 * span : span;
+    float *taps = (float *)malloc(sizeof(float) * ntaps_dev);
     if (!taps) {
         free(tw);
         pfb_free(p);
@@ -360,18 +366,25 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
     if (dft_mode == RF_DFT_FFT_F32) {
         rfk::pfb_twiddle_fill(nchan, tw);
         memcpy(taps, proto, sizeof(float) * span);
+        if (ntaps_dev > span) {
+            const int L = nchan / fir_c;
+            for (int c = 0; c < L; ++c)
+                for (int m = 0; m < ntaps; ++m)
+                    for (int k = 0; k < fir_c; ++k)
+                        taps[span + ((size_t)c * ntaps + m) * fir_c + k] = proto[(size_t)m * nchan + c + k * L];
+        }
     } else {
         rfk::pfb_mfma_table_fill(nchan, mfma_exp, tw);
         for (size_t i = 0; i < span; ++i) taps[i] = ldexpf(proto[i], mfma_exp);
     }
-    if ((rc = dev_alloc(&p->d_taps, span, "taps")) || (rc = dev_alloc(&p->d_tw, 2 * (size_t)ntw, "twiddles")) ||
+    if ((rc = dev_alloc(&p->d_taps, ntaps_dev, "taps")) || (rc = dev_alloc(&p->d_tw, 2 * (size_t)ntw, "twiddles")) ||
         (rc = dev_alloc(&p->d_hist[0], span, "history")) || (rc = dev_alloc(&p->d_hist[1], span, "history"))) {
         free(tw);
         free(taps);
         pfb_free(p);
         return rc;
     }
-    e = hipMemcpy(p->d_taps, taps, span * sizeof(float), hipMemcpyHostToDevice);
+    e = hipMemcpy(p->d_taps, taps, ntaps_dev * sizeof(float), hipMemcpyHostToDevice);
     free(taps);
     if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw, sizeof(float) * 2 * ntw, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->order.ev, hipEventDisableTiming);

@@ -41,7 +41,8 @@ def test_pfb_small_workload_parity():
 
 
 SHAPES = [(16, 1), (16, 4), (32, 3), (64, 2), (64, 8), (128, 5), (256, 8), (256, 16),
-          (512, 4), (1024, 1), (1024, 8), (1024, 16), (2048, 6), (4096, 4), (4096, 8)]
+          (512, 4), (1024, 1), (1024, 8), (1024, 16), (2048, 6), (4096, 1), (4096, 4), (4096, 8),
+          (4096, 16)]
 
 
 @pytest.mark.parametrize("N,M", SHAPES)
