@@ -787,6 +787,18 @@ def bench_serving(rf, torch, seconds):
         r = serve.run(specs, arrivals, pool, m, realtime=False)
         res[name]["saturation_msamples_per_s"] = r["msamples_per_s"]
         log("serving %s saturation: %.0f Msamples/s" % (name, r["msamples_per_s"]))
+    # the same arrivals from pinned host memory: each buffer is copied to a
+    # device staging slot by the server's copy stream (PCIe inside the latency)
+    host_pool = torch.empty(pool.shape, dtype=pool.dtype, pin_memory=True)
+    host_pool.copy_(pool)
+    torch.cuda.synchronize()
+    for name, m in (("graph", rf.RFS_MODE_GRAPH), ("sequential", rf.RFS_MODE_SEQUENTIAL)):
+        r = serve.run(specs, arrivals, host_pool, m, realtime=True, host_slots=2)
+        res[name + "_host_arrivals"] = {"latency_ms": r["latency_ms"], "msamples_per_s": r["msamples_per_s"],
+                                        "batches": r["batches"]}
+        log("serving %s, host arrivals: p50 %.2f ms p99 %.2f ms"
+            % (name, r["latency_ms"]["p50"], r["latency_ms"]["p99"]))
+    del host_pool
     return res
 
 

@@ -339,9 +339,14 @@ int ddc_tuned_config(rf_ddc_t ddc, int32_t *grid);
  * that arrive while a batch is on the GPU join the next one.  Streams are
  * admitted by their device-memory footprint against a budget.
  *
- * Input buffers are device pointers owned by the caller, kept alive until the
- * request completes.  Results stay in the stream's output slot until the
- * caller releases it (rfs_release).  All calls are thread-safe.
+ * Input buffers are owned by the caller and kept alive until the request
+ * completes.  They are device memory, or pinned host memory (hipHostMalloc)
+ * for streams opened with host_slots > 0: the server copies such a buffer
+ * into one of the stream's device staging slots on a copy stream of its own,
+ * overlapped with the running batch, and the batch that uses it waits for
+ * that copy only (the paper's host RAM -> GPU hop, Sec. II.B and Fig. 2).
+ * Results stay in the stream's output slot until the caller releases it
+ * (rfs_release).  All calls are thread-safe.
  */
 typedef struct rfs_server *rfs_t;
 
@@ -364,6 +369,8 @@ typedef struct {
     int32_t decim;            /* DDC: D */
     uint64_t max_buffer;      /* largest nsamples of one request */
     int32_t out_slots;        /* output slots of the stream, >= 1 */
+    int32_t host_slots;       /* device staging slots for pinned-host buffers
+                                 (max_buffer samples each), 0 = device buffers only */
 } rfs_stream_desc;
 
 typedef struct {
@@ -393,7 +400,8 @@ typedef struct {
  * open streams.  Starts the scheduler thread. */
 int rfs_create(rfs_t *out, uint64_t hbm_budget_bytes, int32_t mode, int32_t max_streams);
 
-/* Device bytes a stream with this description occupies (state + output slots). */
+/* Device bytes a stream with this description occupies (state, output slots
+ * and staging slots). */
 uint64_t rfs_stream_footprint(const rfs_stream_desc *desc);
 
 /* Open a stream; *id receives its number.  RF_EAGAIN when its footprint does
@@ -401,8 +409,11 @@ uint64_t rfs_stream_footprint(const rfs_stream_desc *desc);
  * close); RF_EINVAL for a bad description. */
 int rfs_open_stream(rfs_t s, const rfs_stream_desc *desc, int32_t *id);
 
-/* Queue the next buffer of stream `id` (device pointer, nsamples <= max_buffer). */
-int rfs_submit(rfs_t s, int32_t id, const int16_t *iq_dev, uint64_t nsamples, uint64_t tag);
+/* Queue the next buffer of stream `id` (nsamples <= max_buffer): a device
+ * pointer, or a pinned-host pointer when the stream has host_slots.  RF_EINVAL
+ * for pageable host memory, for a pinned-host pointer on a stream without
+ * staging slots, or for a misaligned pointer. */
+int rfs_submit(rfs_t s, int32_t id, const int16_t *iq, uint64_t nsamples, uint64_t tag);
 
 /* Collect up to `max` completions, waiting up to timeout_us (0: do not wait). */
 int rfs_poll(rfs_t s, rfs_completion *out, int32_t max, int32_t *count, int32_t timeout_us);

@@ -44,7 +44,8 @@ class StreamDesc(ctypes.Structure):
                 ("proto", ctypes.c_void_p), ("ntones", ctypes.c_int32),
                 ("phase_inc", ctypes.c_void_p), ("phase0", ctypes.c_void_p),
                 ("lpf_taps", ctypes.c_int32), ("lpf", ctypes.c_void_p), ("decim", ctypes.c_int32),
-                ("max_buffer", ctypes.c_uint64), ("out_slots", ctypes.c_int32)]
+                ("max_buffer", ctypes.c_uint64), ("out_slots", ctypes.c_int32),
+                ("host_slots", ctypes.c_int32)]
 
 
 class Completion(ctypes.Structure):
@@ -490,8 +491,9 @@ class Server:
         self._poll_buf = (Completion * 256)()
 
     @staticmethod
-    def make_desc(pfb=None, ddc=None, max_buffer=1 << 20, out_slots=2):
-        """pfb=(N, M, proto); ddc=(words, phase0 or None, lpf, D).  Returns (desc, keepalive)."""
+    def make_desc(pfb=None, ddc=None, max_buffer=1 << 20, out_slots=2, host_slots=0):
+        """pfb=(N, M, proto); ddc=(words, phase0 or None, lpf, D); host_slots: device
+        staging slots for pinned-host submissions.  Returns (desc, keepalive)."""
         import numpy as np
         d = StreamDesc()
         keep = []
@@ -514,6 +516,7 @@ class Server:
             d.lpf_taps, d.lpf, d.decim = int(lpf.size), lpf.ctypes.data, int(D)
         d.max_buffer = int(max_buffer)
         d.out_slots = int(out_slots)
+        d.host_slots = int(host_slots)
         return d, keep
 
     @staticmethod

@@ -45,6 +45,8 @@ struct Request {
     uint64_t n;
     uint64_t tag;
     double t_submit;
+    bool host = false;         // pinned host memory: staged before use
+    int stage = -1;            // staging slot holding its copy (host requests, once issued)
 };
 
 struct Stream {
@@ -59,6 +61,11 @@ struct Stream {
     int nslots = 0;
     std::vector<float *> pfb_slot, ddc_slot;
     std::vector<int> free_slots;
+    // staging slots for pinned-host buffers: device copies, each with the
+    // event that marks its copy's completion on the server's copy stream
+    std::vector<uint32_t *> stage_buf;
+    std::vector<hipEvent_t> stage_ev;
+    std::vector<int> free_stage;
     std::deque<Request> queue;
     int inflight = 0;
     size_t footprint = 0;
@@ -66,7 +73,9 @@ struct Stream {
 };
 
 struct Done {
-    int stream, slot;
+    int stream, slot, stage;
+    int tp = -1, td = -1;      // item tables (PFB, DDC) of a grouped batch, or -1
+    bool reported = false;
     Request req;
     uint64_t pfb_frames, ddc_outputs, ddc_ld;
     const float *pfb_out, *ddc_out;
@@ -85,6 +94,9 @@ struct Blob {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_version = -1;
+    // completion of each table's grouped kernel (recorded on its branch), so
+    // that a request completes when its own kernels finish, not the batch's
+    std::vector<hipEvent_t> tev;
 };
 
 }  // namespace
@@ -96,6 +108,7 @@ struct rfs_server {
     int cus = 256;
     uint64_t budget = 0, admitted = 0;
     hipStream_t hs = nullptr;
+    hipStream_t cs = nullptr;          // host-to-device copies of pinned-host buffers
     std::vector<hipStream_t> branch;   // fork streams for graph capture
     std::vector<hipEvent_t> fork_ev;
     std::mutex mu;
@@ -156,6 +169,7 @@ size_t footprint_of(const rfs_stream_desc *d)
         f += rfi::ddc_footprint(d->ntones, d->lpf_taps);
         f += (size_t)slots * d->ntones * slot_outputs(d->lpf_taps, d->decim, d->max_buffer) * 8;
     }
+    if (d->host_slots > 0) f += (size_t)d->host_slots * d->max_buffer * 4;
     return f;
 }
 
@@ -166,6 +180,8 @@ void free_stream(Stream *s)
     if (s->ddc) ddc_destroy(s->ddc);
     for (float *p : s->pfb_slot) (void)hipFree(p);
     for (float *p : s->ddc_slot) (void)hipFree(p);
+    for (uint32_t *p : s->stage_buf) (void)hipFree(p);
+    for (hipEvent_t e : s->stage_ev) (void)hipEventDestroy(e);
     delete s;
 }
 
@@ -243,6 +259,7 @@ int capture_graph(rfs_server *S, Blob &b)
         else
             err = rfk::launch_ddc_group(S->ddc_classes[t - C], h, items_at<rfk::DdcItem>(b.dev, S->region, t),
                                         S->cus, bs);
+        if (err == hipSuccess) err = hipEventRecord(b.tev[t], bs);
     }
     const int used = std::min(NT, kMaxBranches);   // join only the branches the capture forked
     for (int k = 0; k < used && err == hipSuccess; ++k) {
@@ -266,15 +283,38 @@ int capture_graph(rfs_server *S, Blob &b)
     return RF_OK;
 }
 
+// Issue the host-to-device copies of queued pinned-host buffers, in queue
+// order, into free staging slots (caller holds mu).  The copies run on the
+// copy stream, overlapped with the batch in flight.
+int stage_copies(rfs_server *S)
+{
+    for (auto &kv : S->streams) {
+        Stream *s = kv.second;
+        for (Request &r : s->queue) {
+            if (!r.host || r.stage >= 0) continue;
+            if (s->free_stage.empty()) break;
+            const int k = s->free_stage.back();
+            if (hipMemcpyAsync(s->stage_buf[k], r.iq, r.n * 4, hipMemcpyHostToDevice, S->cs) != hipSuccess ||
+                hipEventRecord(s->stage_ev[k], S->cs) != hipSuccess)
+                return set_error(RF_EDEVICE, "staging copy failed");
+            s->free_stage.pop_back();
+            r.stage = k;
+        }
+    }
+    return RF_OK;
+}
+
 // Pick one request per eligible stream and prepare its launches (caller holds
-// mu).  SEQUENTIAL mode takes only the oldest request overall.
+// mu).  SEQUENTIAL mode takes only the oldest request overall.  A pinned-host
+// request is eligible once its staging copy has been issued.
 bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunch> &pl,
                 std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who)
 {
     std::vector<Stream *> cand;
     for (auto &kv : S->streams) {
         Stream *s = kv.second;
-        if (!s->queue.empty() && !s->free_slots.empty()) cand.push_back(s);
+        if (!s->queue.empty() && !s->free_slots.empty() && (!s->queue.front().host || s->queue.front().stage >= 0))
+            cand.push_back(s);
     }
     if (cand.empty()) return false;
     std::sort(cand.begin(), cand.end(),
@@ -286,7 +326,9 @@ bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunc
         Done d{};
         d.stream = s->id;
         d.slot = slot;
+        d.stage = r.host ? r.stage : -1;
         d.req = r;
+        if (r.host) r.iq = reinterpret_cast<const int16_t *>(s->stage_buf[r.stage]);
         rfk::PfbLaunch a{};
         rfk::DdcLaunch b{};
         bool ok = true;
@@ -304,6 +346,7 @@ bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunc
             d.ddc_out = s->ddc_slot[slot];
         }
         if (!ok) {   // cannot happen for validated submissions; drop the request with an error
+            if (d.stage >= 0) s->free_stage.push_back(d.stage);
             s->queue.pop_front();
             rfs_completion c{};
             c.stream = s->id;
@@ -331,7 +374,14 @@ bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunc
 int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk::PfbLaunch> &pl,
                  std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who)
 {
-    if (S->mode == RFS_MODE_SEQUENTIAL) {
+    // the batch reads staged copies: wait for those copies (only)
+    for (size_t i = 0; i < who.size(); ++i)
+        if (dn[i].stage >= 0 && hipStreamWaitEvent(S->hs, who[i]->stage_ev[dn[i].stage], 0) != hipSuccess)
+            return set_error(RF_EDEVICE, "wait for staging copy failed");
+    // A batch of one request (the common case at light load) gains nothing
+    // from item tables, grouped kernels or a graph: it is launched as the
+    // single-stream kernels, which compute the same results bit for bit.
+    if (S->mode == RFS_MODE_SEQUENTIAL || who.size() == 1) {
         for (size_t i = 0; i < who.size(); ++i) {
             Stream *s = who[i];
             if (s->pfb && dn[i].req.n) {
@@ -367,6 +417,7 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
             it.wgs = (int32_t)rfk::pfb_launch_wgs(pl[i]);
             h->total += it.wgs;
             h->count++;
+            dn[i].tp = t;
         }
         if (s->ddc) {
             const int t = C + ddc_class_index(S, s->ntones);
@@ -376,6 +427,7 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
             it.unit_begin = h->total;
             h->total += rfk::ddc_group_units(dl[i]);
             h->count++;
+            dn[i].td = t;
         }
     }
     if (S->mode == RFS_MODE_GRAPH) {
@@ -387,21 +439,33 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
     } else {
         hipError_t e = hipMemcpyAsync(b.dev, b.host, S->region * NT, hipMemcpyHostToDevice, S->hs);
         if (e != hipSuccess) return set_error(RF_EDEVICE, "table upload failed");
-        for (int t = 0; t < NT; ++t) {
+        // one branch per table, as in the captured graph; then join
+        e = hipEventRecord(S->fork_ev[0], S->hs);
+        int used = 0;
+        for (int t = 0; t < NT && e == hipSuccess; ++t) {
             const rfk::GroupHeader *hh = hdr_at(b.host, S->region, t);
             if (hh->count == 0) continue;
+            hipStream_t bs = S->branch[used % kMaxBranches];
+            ++used;
+            e = hipStreamWaitEvent(bs, S->fork_ev[0], 0);
+            if (e != hipSuccess) break;
             const rfk::GroupHeader *hd = hdr_at(b.dev, S->region, t);
             if (t < C) {
                 const int grid = (int)std::min<int64_t>(hh->total, pfb_grid(S, S->classes[t].first));
                 e = rfk::launch_pfb_group(S->classes[t].first, S->classes[t].second, hd,
-                                          items_at<rfk::PfbItem>(b.dev, S->region, t), grid, S->hs);
+                                          items_at<rfk::PfbItem>(b.dev, S->region, t), grid, bs);
             } else {
                 const int grid = (int)std::min<int64_t>(hh->total, S->cus);
                 e = rfk::launch_ddc_group(S->ddc_classes[t - C], hd, items_at<rfk::DdcItem>(b.dev, S->region, t),
-                                          grid, S->hs);
+                                          grid, bs);
             }
-            if (e != hipSuccess) return set_error(RF_EDEVICE, "grouped launch failed");
+            if (e == hipSuccess) e = hipEventRecord(b.tev[t], bs);
         }
+        for (int k = 0; k < std::min(used, kMaxBranches) && e == hipSuccess; ++k) {
+            e = hipEventRecord(S->fork_ev[1 + k], S->branch[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(S->hs, S->fork_ev[1 + k], 0);
+        }
+        if (e != hipSuccess) return set_error(RF_EDEVICE, "grouped launch failed");
     }
     for (size_t i = 0; i < who.size(); ++i) {
         Stream *s = who[i];
@@ -412,31 +476,59 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
     return RF_OK;
 }
 
+// Report one request's completion (caller holds mu).
+void report(rfs_server *S, Done &d, double t)
+{
+    rfs_completion c{};
+    c.stream = d.stream;
+    c.slot = d.slot;
+    c.tag = d.req.tag;
+    c.nsamples = d.req.n;
+    c.status = RF_OK;
+    c.pfb_frames = d.pfb_frames;
+    c.pfb_out = d.pfb_out;
+    c.ddc_outputs = d.ddc_outputs;
+    c.ddc_ld = d.ddc_ld;
+    c.ddc_out = d.ddc_out;
+    c.t_submit = d.req.t_submit;
+    c.t_launch = d.t_launch;
+    c.t_done = t;
+    S->completions.push_back(c);
+    auto it = S->streams.find(d.stream);
+    if (it != S->streams.end()) {
+        it->second->inflight--;
+        if (d.stage >= 0) it->second->free_stage.push_back(d.stage);
+    }
+    S->st.requests++;
+    S->st.samples += d.req.n;
+    d.reported = true;
+}
+
+// Requests of a running grouped batch whose own kernels have finished.
+void report_early(rfs_server *S, Blob &b)
+{
+    bool any = false;
+    double t = 0;
+    for (Done &d : b.done) {
+        if (d.reported || (d.tp < 0 && d.td < 0)) continue;
+        if (d.tp >= 0 && hipEventQuery(b.tev[d.tp]) != hipSuccess) continue;
+        if (d.td >= 0 && hipEventQuery(b.tev[d.td]) != hipSuccess) continue;
+        if (!any) {
+            t = now_s();
+            any = true;
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        report(S, d, t);
+    }
+    if (any) S->cv_done.notify_all();
+}
+
 void finish_blob(rfs_server *S, Blob &b)
 {
     const double t = now_s();
     std::lock_guard<std::mutex> lk(S->mu);
-    for (Done &d : b.done) {
-        rfs_completion c{};
-        c.stream = d.stream;
-        c.slot = d.slot;
-        c.tag = d.req.tag;
-        c.nsamples = d.req.n;
-        c.status = RF_OK;
-        c.pfb_frames = d.pfb_frames;
-        c.pfb_out = d.pfb_out;
-        c.ddc_outputs = d.ddc_outputs;
-        c.ddc_ld = d.ddc_ld;
-        c.ddc_out = d.ddc_out;
-        c.t_submit = d.req.t_submit;
-        c.t_launch = d.t_launch;
-        c.t_done = t;
-        S->completions.push_back(c);
-        auto it = S->streams.find(d.stream);
-        if (it != S->streams.end()) it->second->inflight--;
-        S->st.requests++;
-        S->st.samples += d.req.n;
-    }
+    for (Done &d : b.done)
+        if (!d.reported) report(S, d, t);
     S->st.batches++;
     S->st.gpu_busy_seconds += t - b.t_launch;
     b.done.clear();
@@ -455,7 +547,9 @@ void scheduler(rfs_server *S)
         // retire finished batches, oldest first
         for (int k = 0; k < 2; ++k) {
             Blob &b = S->blobs[(S->next_blob + k) & 1];
-            if (b.busy && hipEventQuery(b.ev) == hipSuccess) finish_blob(S, b);
+            if (!b.busy) continue;
+            if (hipEventQuery(b.ev) == hipSuccess) finish_blob(S, b);
+            else report_early(S, b);
         }
         Blob &b = S->blobs[S->next_blob];
         if (b.busy) {   // both blobs in flight: wait for the older one
@@ -472,6 +566,11 @@ void scheduler(rfs_server *S)
                 bool pending = false;
                 for (auto &kv : S->streams) pending |= !kv.second->queue.empty();
                 if (!pending) break;
+            }
+            if (stage_copies(S)) {
+                S->fatal = rf_last_error();
+                S->stop = true;
+                break;
             }
             if (!form_batch(S, dn, pl, dl, who)) {
                 const bool any_busy = S->blobs[0].busy || S->blobs[1].busy;
@@ -531,6 +630,7 @@ int rfs_create(rfs_t *out, uint64_t hbm_budget_bytes, int32_t mode, int32_t max_
     if (ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && cus > 0)
         S->cus = cus;
     ok = ok && hipStreamCreateWithFlags(&S->hs, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) == hipSuccess;
     for (int k = 0; ok && k < kMaxBranches; ++k) {
         hipStream_t bs = nullptr;
         ok = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) == hipSuccess;
@@ -551,6 +651,11 @@ int rfs_create(rfs_t *out, uint64_t hbm_budget_bytes, int32_t mode, int32_t max_
         ok = hipHostMalloc(&b.host, bytes, hipHostMallocDefault) == hipSuccess &&
              hipMalloc(&b.dev, bytes) == hipSuccess &&
              hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess;
+        for (int t = 0; ok && t < max_streams + 5; ++t) {
+            hipEvent_t ev = nullptr;
+            ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+            if (ok) b.tev.push_back(ev);
+        }
         if (ok) memset(b.host, 0, bytes);
     }
     if (!ok) {
@@ -570,6 +675,7 @@ int rfs_open_stream(rfs_t S, const rfs_stream_desc *d, int32_t *id)
     if (!(d->kinds & (RFS_PFB | RFS_DDC)) || (d->kinds & ~(RFS_PFB | RFS_DDC)))
         return set_error(RF_EINVAL, "rfs_open_stream: kinds must be RFS_PFB and/or RFS_DDC");
     if (d->max_buffer < 1) return set_error(RF_EINVAL, "rfs_open_stream: max_buffer must be >= 1");
+    if (d->host_slots < 0 || d->host_slots > 64) return set_error(RF_EINVAL, "rfs_open_stream: host_slots must be in [0, 64]");
     if ((d->kinds & RFS_PFB) && (d->nchan < 16 || d->nchan > 4096 || (d->nchan & (d->nchan - 1))))
         return set_error(RF_EINVAL, "rfs_open_stream: served PFB streams need a power-of-two nchan in [16, 4096]");
     const size_t fp = footprint_of(d);
@@ -615,6 +721,21 @@ int rfs_open_stream(rfs_t S, const rfs_stream_desc *d, int32_t *id)
             }
         }
         for (int k = 0; k < s->nslots; ++k) s->free_slots.push_back(s->nslots - 1 - k);
+        for (int k = 0; !rc && k < d->host_slots; ++k) {
+            uint32_t *p = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipMalloc((void **)&p, d->max_buffer * 4) != hipSuccess) {
+                rc = set_error(RF_ENOMEM, "rfs_open_stream: staging slot allocation");
+                break;
+            }
+            s->stage_buf.push_back(p);
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                rc = set_error(RF_EDEVICE, "rfs_open_stream: staging event");
+                break;
+            }
+            s->stage_ev.push_back(ev);
+            s->free_stage.push_back(d->host_slots - 1 - k);
+        }
     }
     std::lock_guard<std::mutex> lk(S->mu);
     if (rc) {
@@ -631,18 +752,32 @@ int rfs_open_stream(rfs_t S, const rfs_stream_desc *d, int32_t *id)
     return RF_OK;
 }
 
-int rfs_submit(rfs_t S, int32_t id, const int16_t *iq_dev, uint64_t nsamples, uint64_t tag)
+int rfs_submit(rfs_t S, int32_t id, const int16_t *iq, uint64_t nsamples, uint64_t tag)
 {
     if (!S) return set_error(RF_EINVAL, "rfs_submit: server is NULL");
+    bool host = false;
+    if (nsamples > 0) {
+        if (!iq || ((uintptr_t)iq & 3)) return set_error(RF_EINVAL, "rfs_submit: iq must be a non-NULL 4-byte aligned pointer");
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, iq) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(RF_EINVAL, "rfs_submit: iq is neither device memory nor pinned host memory");
+        }
+        if (at.type == hipMemoryTypeHost) host = true;
+        else if (at.type != hipMemoryTypeDevice)
+            return set_error(RF_EINVAL, "rfs_submit: iq is neither device memory nor pinned host memory");
+    }
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return set_error(RF_EDEVICE, S->fatal.empty() ? "rfs_submit: server stopped" : S->fatal.c_str());
     auto it = S->streams.find(id);
     if (it == S->streams.end() || it->second->closing) return set_error(RF_EINVAL, "rfs_submit: unknown stream");
     Stream *s = it->second;
     if (nsamples > s->max_buffer) return set_error(RF_EINVAL, "rfs_submit: nsamples exceeds the stream's max_buffer");
-    if (nsamples > 0 && (!iq_dev || ((uintptr_t)iq_dev & 3)))
-        return set_error(RF_EINVAL, "rfs_submit: iq_dev must be a non-NULL 4-byte aligned device pointer");
-    s->queue.push_back(Request{iq_dev, nsamples, tag, now_s()});
+    if (host && s->stage_buf.empty())
+        return set_error(RF_EINVAL, "rfs_submit: pinned-host buffer on a stream opened without host_slots");
+    Request r{iq, nsamples, tag, now_s()};
+    r.host = host;
+    s->queue.push_back(r);
     S->cv_work.notify_one();
     return RF_OK;
 }
@@ -715,6 +850,7 @@ int rfs_destroy(rfs_t S)
         S->thr.join();
     }
     if (S->hs) (void)hipStreamSynchronize(S->hs);
+    if (S->cs) (void)hipStreamSynchronize(S->cs);
     for (auto &kv : S->streams) free_stream(kv.second);
     for (int k = 0; k < 2; ++k) {
         Blob &b = S->blobs[k];
@@ -723,10 +859,12 @@ int rfs_destroy(rfs_t S)
         if (b.host) (void)hipHostFree(b.host);
         if (b.dev) (void)hipFree(b.dev);
         if (b.ev) (void)hipEventDestroy(b.ev);
+        for (hipEvent_t e : b.tev) (void)hipEventDestroy(e);
     }
     for (hipEvent_t e : S->fork_ev) (void)hipEventDestroy(e);
     for (hipStream_t bs : S->branch) (void)hipStreamDestroy(bs);
     if (S->hs) (void)hipStreamDestroy(S->hs);
+    if (S->cs) (void)hipStreamDestroy(S->cs);
     delete S;
     return RF_OK;
 }

@@ -18,19 +18,21 @@ from . import _lib
 
 
 def run(specs, arrivals, pool, mode: int, budget: int = 48 << 30, realtime: bool = True,
-        collect: bool = False, out_slots: int = 3, max_streams: int = 64) -> Dict:
+        collect: bool = False, out_slots: int = 3, max_streams: int = 64, host_slots: int = 0) -> Dict:
     """Open the streams on a fresh server, replay the arrivals and collect completions.
 
     realtime: submit each buffer at its arrival time (latency run); otherwise
     submit everything at once (saturation run).  collect: copy every output to
-    the host (for parity checks) before releasing its slot.
+    the host (for parity checks) before releasing its slot.  host_slots: staging
+    slots per stream, needed when `pool` is pinned host memory.
     """
     import torch
     srv = _lib.Server(budget, mode, max_streams)
     ids = []
     for sp in specs:
         desc, keep = _lib.Server.make_desc(
-            pfb=(sp.N, sp.M, sp.proto), ddc=sp.ddc, max_buffer=sp.max_buffer, out_slots=out_slots)
+            pfb=(sp.N, sp.M, sp.proto), ddc=sp.ddc, max_buffer=sp.max_buffer, out_slots=out_slots,
+            host_slots=host_slots)
         ids.append(srv.open_stream(desc, keep))
     base = pool.data_ptr()
     lat, outputs = [], {}

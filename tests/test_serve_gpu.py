@@ -138,3 +138,124 @@ def test_serve_admission_by_footprint_and_close():
         srv.submit(b, buf.data_ptr(), (1 << 20) + 1, 0)    # larger than max_buffer
     srv.close()
     torch.cuda.synchronize()
+
+
+def _mix_arrivals(specs, sizes, pool_n, seed=3):
+    from siggen import mix
+    rng = np.random.default_rng(seed)
+    mix_specs, arrivals = [], []
+    for s, sp in enumerate(specs):
+        off = int(rng.integers(0, pool_n - sum(sizes[s]) + 1))
+        mix_specs.append(mix.StreamSpecMix(sp["N"], sp["M"], sp["h"], sp["ddc"], off, max(sizes[s])))
+        pos = off
+        for n in sizes[s]:
+            arrivals.append(mix.Arrival(0.0, s, n, pos))
+            pos += n
+    return mix_specs, arrivals
+
+
+@pytest.mark.parametrize("mode", ["sequential", "batched", "graph"])
+def test_serve_pinned_host_buffers_equal_device_buffers(mode):
+    """The same streams submitted from pinned host memory (staged by the
+    server's copy stream) and from device memory give bit-identical results."""
+    rf = _rf()
+    import torch
+
+    from paper_1812_02200_amd import serve
+    specs, sizes = small_mix(seed=11)
+    pool_n = 1 << 20
+    pool = siggen.iq_torch(siggen.StreamSpec(13, siggen.pfb_small().stream.tones, 700.0), 0, pool_n)
+    host_pool = torch.empty(pool.shape, dtype=pool.dtype, pin_memory=True)
+    host_pool.copy_(pool)
+    torch.cuda.synchronize()
+    mix_specs, arrivals = _mix_arrivals(specs, sizes, pool_n)
+    m = {"sequential": rf.RFS_MODE_SEQUENTIAL, "batched": rf.RFS_MODE_BATCHED, "graph": rf.RFS_MODE_GRAPH}[mode]
+    dev = serve.run(mix_specs, arrivals, pool, m, budget=8 << 30, realtime=False, collect=True)
+    host = serve.run(mix_specs, arrivals, host_pool, m, budget=8 << 30, realtime=False, collect=True,
+                     host_slots=2)
+    log("pinned-host vs device (%s): %d requests" % (mode, len(arrivals)))
+    for s, sp in enumerate(specs):
+        assert len(host["outputs"][s]) == len(dev["outputs"][s]) == len(sizes[s])
+        for g, r in zip(host["outputs"][s], dev["outputs"][s]):
+            assert np.array_equal(g["pfb"].view(np.uint64), r["pfb"].view(np.uint64)), (mode, s)
+            if sp["ddc"] is not None:
+                assert np.array_equal(g["ddc"].view(np.uint64), r["ddc"].view(np.uint64)), (mode, s)
+
+
+def test_serve_rejects_unstaged_and_pageable_host_buffers():
+    rf = _rf()
+    import torch
+    h = siggen.pfb_prototype(256, 4)
+    d0, k0 = rf.Server.make_desc(pfb=(256, 4, h), max_buffer=1 << 16, out_slots=1)
+    d2, k2 = rf.Server.make_desc(pfb=(256, 4, h), max_buffer=1 << 16, out_slots=1, host_slots=2)
+    assert rf.Server.footprint(d2) == rf.Server.footprint(d0) + 2 * (1 << 16) * 4
+    srv = rf.Server(1 << 30, rf.RFS_MODE_BATCHED, 4)
+    a = srv.open_stream(d0, k0)
+    pinned = torch.zeros(2 << 16, dtype=torch.int16, pin_memory=True)
+    pageable = np.zeros(2 << 16, dtype=np.int16)
+    with pytest.raises(rf.RfError) as ei:
+        srv.submit(a, pinned.data_ptr(), 1 << 16, 0)        # stream has no staging slots
+    assert ei.value.status == rf.RF_EINVAL
+    b = srv.open_stream(d2, k2)
+    with pytest.raises(rf.RfError) as ei:
+        srv.submit(b, pageable.ctypes.data, 1 << 16, 0)     # pageable host memory
+    assert ei.value.status == rf.RF_EINVAL
+    srv.submit(b, pinned.data_ptr(), 1 << 16, 7)
+    got = []
+    while not got:
+        got = srv.poll(8, 100000)
+    assert got[0]["tag"] == 7 and got[0]["status"] == 0
+    srv.release(b, got[0]["slot"])
+    srv.close()
+    torch.cuda.synchronize()
+
+
+def test_serve_served_mix_shape_equals_alone():
+    """The served-mix shape: 16 streams, N in {64, 256, 1024, 4096}, M in
+    {4, 8}, half with DDC banks (one of 2000 tones, 1024-tap low-pass,
+    decimation 1000), buffers of 2^16 .. 2^24 samples, N = 4096 at M = 8
+    among them; every stream's results in the mix equal the same stream alone,
+    bit for bit, in the captured-graph mode."""
+    rf = _rf()
+    import torch
+
+    from paper_1812_02200_amd import serve
+    rng = np.random.default_rng(21)
+    shapes = [(64, 4), (64, 8), (256, 4), (256, 8), (1024, 4), (1024, 8), (4096, 4), (4096, 8)] * 2
+    tones = [0, 2000, 0, 10, 0, 300, 0, 57, 0, 1200, 0, 25, 0, 800, 0, 140]
+    sizes = [[1 << 24, 1 << 16] if s in (6, 7, 13) else [1 << int(rng.integers(16, 21)) for _ in range(2)]
+             for s in range(16)]
+    specs = []
+    for (N, M), nt in zip(shapes, tones):
+        ddc = None
+        if nt:
+            ddc = (siggen.random_words(rng, nt), siggen.random_words(rng, nt),
+                   siggen.ddc_lowpass(1024, 80e3, siggen.FS, "blackman"), 1000)
+        specs.append(dict(N=N, M=M, h=siggen.pfb_prototype(N, M, "kaiser", 9.0), ddc=ddc))
+    assert any(sp["N"] == 4096 and sp["M"] == 8 for sp in specs)
+    pool_n = 3 << 24
+    pool = siggen.iq_torch(siggen.StreamSpec(23, siggen.pfb_small().stream.tones, 300.0), 0, pool_n)
+    mix_specs, arrivals = _mix_arrivals(specs, sizes, pool_n, seed=5)
+    log("served-mix shape: %d streams, %d requests, %.1f Msamples"
+        % (len(specs), len(arrivals), sum(a.nsamples for a in arrivals) / 1e6))
+    res = serve.run(mix_specs, arrivals, pool, rf.RFS_MODE_GRAPH, budget=64 << 30, realtime=False,
+                    collect=True)
+    assert res["requests"] == len(arrivals)
+    for s, sp in enumerate(specs):
+        p = rf.Pfb(sp["N"], sp["M"], sp["h"], max_samples_per_call=max(sizes[s]))
+        d = None
+        if sp["ddc"] is not None:
+            w, p0, lpf, D = sp["ddc"]
+            d = rf.Ddc(w, lpf, D, p0, max_samples_per_call=max(sizes[s]))
+        got = res["outputs"][s]
+        bufs = [a for a in arrivals if a.stream == s]
+        assert len(got) == len(bufs)
+        for g, a in zip(got, bufs):
+            b = pool[2 * a.pool_start: 2 * (a.pool_start + a.nsamples)]
+            y = p.process(b).cpu().numpy()
+            assert np.array_equal(g["pfb"].view(np.uint64), y.view(np.uint64)), s
+            if d is not None:
+                yd = d.process(b).cpu().numpy()
+                assert np.array_equal(g["ddc"].view(np.uint64), yd.view(np.uint64)), s
+        del p, d
+    torch.cuda.synchronize()
