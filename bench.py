@@ -421,8 +421,22 @@ def _trace_frac(kernel, units_per_launch, peak_per_s):
             "source": os.path.relpath(TRACE_PROFILE, ROOT)}
 
 
+def cpu_model():
+    """The host CPU's model name (first processor entry), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_pfb(oracle, w, d, budget_s):
-    """The FP64 oracle on the same stream (host cores), repeated up to ~budget_s."""
+    """The FP64 oracle on the same stream (host cores), repeated up to ~budget_s,
+    then on one thread over a leading part of the frames (~budget_s / 2)."""
     nf = oracle.pfb_nframes(w.nsamples, w.N, w.M)
     iq = d.cpu().numpy()
     frames = np.arange(nf)
@@ -432,10 +446,25 @@ def cpu_pfb(oracle, w, d, budget_s):
         oracle.pfb(w.h, w.N, w.M, iq=iq, frames=frames)
         t += time.perf_counter() - t0
         reps += 1
-    return {"value": reps * nf * w.N / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": t,
+    cores = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        k = 256
+        t0 = time.perf_counter()
+        oracle.pfb(w.h, w.N, w.M, iq=iq, frames=np.arange(k))
+        t1 = time.perf_counter() - t0
+        k = int(min(nf, max(k, k * 0.5 * budget_s / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.pfb(w.h, w.N, w.M, iq=iq, frames=np.arange(k))
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": reps * nf * w.N / t / 1e6, "unit": "Msamples/s", "cores": cores,
+            "kind": "oracle", "seconds": t, "cpu_model": cpu_model(),
             "sample": "all %d frames of the 2^28-sample N=1024 M=8 stream x %d passes, FP64, "
-                      "OpenMP over frames" % (nf, reps)}
+                      "OpenMP over frames" % (nf, reps),
+            "single_thread": {"value": k * w.N / t1 / 1e6, "unit": "Msamples/s", "cores": 1, "seconds": t1,
+                              "sample": "the first %d frames of the same stream, FP64, one thread" % k}}
 
 
 # ------------------------------------------------------------------ DDC
@@ -684,6 +713,7 @@ def cpu_tx(oracle, w, amp, budget_s):
         k = int(max(k, k * budget_s / max(t, 1e-6)))
         t = run(k)
     return {"value": k / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "seconds": t, "sample": "first %d samples of the 1000-tone buffer, FP32 as the kernel, "
                                     "OpenMP over samples" % k}
 
@@ -821,7 +851,7 @@ def cpu_ddc(oracle, w, d, budget_s):
     t = run(k)
     # k outputs of every tone cover k*D input samples of the 1000-tone bank
     return {"value": k * w.D / t / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": t,
+            "kind": "oracle", "seconds": t, "cpu_model": cpu_model(),
             "sample": "first %d outputs of all %d tones (%d input samples), FP64, OpenMP over points"
                       % (k, ntones, k * w.D)}
 
