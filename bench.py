@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "pfb", "ddc", "tx", "large", "precision", "serving", "copyprobe"])
+                    help="comma-separated legs: all, pfb, ddc, tx, large, precision, serving, copyprobe")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -886,10 +886,19 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {}, "device": torch.cuda.get_device_name(0)}
     keep = {}
-    if a.workload == "copyprobe":
+    legs = set(a.workload.split(","))
+    bad = legs - {"all", "pfb", "ddc", "tx", "large", "precision", "serving", "copyprobe"}
+    if bad or ("copyprobe" in legs and len(legs) > 1):
+        print(json.dumps({"error": "unknown or mixed workloads: %s" % a.workload}))
+        sys.exit(2)
+
+    def want(leg):
+        return "all" in legs or leg in legs
+
+    if legs == {"copyprobe"}:
         print(json.dumps(bench_copyprobe(torch)))
         return
-    if a.workload in ("all", "pfb"):
+    if want("pfb"):
         r, keep["pfb"] = bench_pfb(rf, torch, siggen, a.steps, a.warmup)
         rec["value"] = r["value"]
         rec["ms_per_step"] = r["ms_per_step"]
@@ -901,7 +910,7 @@ def main():
             rec["pfb"]["pcie_inclusive"] = bench_pcie(rf, torch, siggen, max(1, min(a.steps, 3)))
             log("pfb from pinned host memory: %.0f Msamples/s (%.1f GB/s over PCIe)" %
                 (rec["pfb"]["pcie_inclusive"]["value"], rec["pfb"]["pcie_inclusive"]["h2d_gbs"]))
-    if a.workload in ("all", "ddc"):
+    if want("ddc"):
         r, keep["ddc"] = bench_ddc(rf, torch, siggen, a.steps, a.warmup)
         rec["ddc"] = r
         if rec["value"] is None:
@@ -910,22 +919,22 @@ def main():
             rec["config"] = r["config"]
             rec["roofline"] = r["roofline"]
         log("ddc: %.0f Msamples/s, %.1f us/launch" % (r["value"], r["kernel_us"]))
-    if a.workload in ("all", "large"):
+    if want("large"):
         rec["large_n"] = bench_large(rf, torch, siggen, max(1, min(a.steps, 5)), 1)
         log("large N=10^5: %.0f Msamples/s" % rec["large_n"]["value"])
         if rec["value"] is None:
             rec["value"] = rec["large_n"]["value"]
             rec["config"] = rec["large_n"]["config"]
-    if a.workload in ("all", "tx"):
+    if want("tx"):
         r, keep["tx"] = bench_tx(rf, torch, siggen, a.steps, a.warmup)
         rec["tx"] = r
         if rec["value"] is None:
             rec["value"] = r["fixed"]["value"]
             rec["config"] = r["config"]
-    if a.workload in ("all", "precision"):
+    if want("precision"):
         import oracle
         rec["precision"] = bench_precision(rf, torch, siggen, oracle, max(1, min(a.steps, 5)), 1)
-    if a.workload in ("all", "serving"):
+    if want("serving"):
         rec["serving"] = bench_serving(rf, torch, a.serve_seconds)
         rec["p99_buffer_latency_ms"] = rec["serving"]["graph"]["latency_ms"]["p99"]
     if not a.no_cpu_baseline:
