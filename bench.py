@@ -75,13 +75,19 @@ def parse():
 
 # ------------------------------------------------------- HBM traffic (PMC)
 
+# The sources the profiled kernels (the timed PFB and DDC kernels, the MFMA
+# DFT of the precision leg) are compiled from, with their launch code.
+PROFILED_SOURCES = ("fft_device.hpp", "rf_internal.hpp", "pfb_kernels.hpp", "pfb_launch.hip", "pfb_n1024.hip",
+                    "ddc_kernels.hip", "pfb_mfma.hpp", "pfb_mfma.hip", "pfb_mfma_n256.hip")
+
+
 def sources_digest():
-    """SHA-256 over the kernel sources: counters taken on other sources are stale."""
+    """SHA-256 over the profiled kernels' sources: counters and traces taken on
+    other sources are stale."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(KERNEL_SOURCES, "*.hip")) +
-                    glob.glob(os.path.join(KERNEL_SOURCES, "*.hpp"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in sorted(PROFILED_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(KERNEL_SOURCES, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

@@ -439,14 +439,15 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
     } else {
         hipError_t e = hipMemcpyAsync(b.dev, b.host, S->region * NT, hipMemcpyHostToDevice, S->hs);
         if (e != hipSuccess) return set_error(RF_EDEVICE, "table upload failed");
-        // one branch per table, as in the captured graph; then join
+        // the captured graph's topology, launched directly: table t on branch
+        // t mod kMaxBranches (empty tables skipped), then join
         e = hipEventRecord(S->fork_ev[0], S->hs);
         int used = 0;
         for (int t = 0; t < NT && e == hipSuccess; ++t) {
             const rfk::GroupHeader *hh = hdr_at(b.host, S->region, t);
             if (hh->count == 0) continue;
-            hipStream_t bs = S->branch[used % kMaxBranches];
-            ++used;
+            hipStream_t bs = S->branch[t % kMaxBranches];
+            used = std::max(used, t % kMaxBranches + 1);
             e = hipStreamWaitEvent(bs, S->fork_ev[0], 0);
             if (e != hipSuccess) break;
             const rfk::GroupHeader *hd = hdr_at(b.dev, S->region, t);
@@ -461,7 +462,7 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
             }
             if (e == hipSuccess) e = hipEventRecord(b.tev[t], bs);
         }
-        for (int k = 0; k < std::min(used, kMaxBranches) && e == hipSuccess; ++k) {
+        for (int k = 0; k < used && e == hipSuccess; ++k) {
             e = hipEventRecord(S->fork_ev[1 + k], S->branch[k]);
             if (e == hipSuccess) e = hipStreamWaitEvent(S->hs, S->fork_ev[1 + k], 0);
         }
