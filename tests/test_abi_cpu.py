@@ -146,3 +146,25 @@ def test_python_binding_raises_instead_of_falling_back():
         rf.Pfb(100, 4, np.zeros(400))
     with pytest.raises(ValueError):
         rf.Pfb(64, 4, np.zeros(10))
+
+
+def test_stream_footprint_counts_staging_slots_and_eight_column_taps():
+    """Admission arithmetic (host only): pinned-host staging slots add
+    host_slots x max_buffer x 4 bytes; the N = 4096 eight-column kernel's
+    per-thread tap copy doubles the taps; output slots scale the output part."""
+    h = np.zeros(1024 * 8, np.float32)
+    d0, _ = rf.Server.make_desc(pfb=(1024, 8, h), max_buffer=1 << 20, out_slots=2)
+    d3, _ = rf.Server.make_desc(pfb=(1024, 8, h), max_buffer=1 << 20, out_slots=2, host_slots=3)
+    assert rf.Server.footprint(d3) - rf.Server.footprint(d0) == 3 * (1 << 20) * 4
+    d1, _ = rf.Server.make_desc(pfb=(1024, 8, h), max_buffer=1 << 20, out_slots=1)
+    frames = ((1024 * 8 + (1 << 20)) // 1024 + 1)
+    assert rf.Server.footprint(d0) - rf.Server.footprint(d1) == frames * 1024 * 8
+    h4 = np.zeros(4096 * 8, np.float32)
+    h2 = np.zeros(2048 * 8, np.float32)
+    f4, _ = rf.Server.make_desc(pfb=(4096, 8, h4), max_buffer=1 << 20, out_slots=1)
+    f2, _ = rf.Server.make_desc(pfb=(2048, 8, h2), max_buffer=1 << 20, out_slots=1)
+    # state beyond the output slot: taps (x2 at N = 4096), twiddles, two histories
+    s4 = rf.Server.footprint(f4) - ((4096 * 8 + (1 << 20)) // 4096 + 1) * 4096 * 8
+    s2 = rf.Server.footprint(f2) - ((2048 * 8 + (1 << 20)) // 2048 + 1) * 2048 * 8
+    assert s4 - 4 * 4096 * 8 * 4 > 0 and s2 - 3 * 2048 * 8 * 4 > 0
+    assert s4 >= 4 * 4096 * 8 * 4 and s2 < 4 * 2048 * 8 * 4
