@@ -193,9 +193,11 @@ __global__ void __launch_bounds__(WG) ddc_bank(DdcLaunch a)
     ddc_tail<WG>(a, blockIdx.x, gridDim.x);
 }
 
-// Grouped launch over the banks of many streams: the units of item i are its
-// (tone chunk, output) pairs, outputs fastest, then one tail unit; work-group
-// b of G takes the contiguous units [b W / G, (b+1) W / G) of the whole list.
+// Grouped launch over the banks of many streams: the units of a call are its
+// (tone chunk, output) pairs, outputs fastest, then one tail unit; an item
+// holds a contiguous range of a call's units (all of them, or a chunk of a
+// long call spread over several launches); work-group b of G takes the
+// contiguous units [b W / G, (b+1) W / G) of the whole list.
 // The table is the same for every bank and is loaded once per work-group.
 // Grouped banks have linear oscillators (the serving path has no chirps).
 template <int WG>
@@ -217,13 +219,14 @@ __global__ void __launch_bounds__(WG) ddc_group(const GroupHeader *hdr, const Dd
     for (int64_t w = b; w < e;) {
         while (lo + 1 < nitems && items[lo + 1].unit_begin <= w) ++lo;
         const DdcItem &it = items[lo];
-        const int64_t k = w - it.unit_begin;
+        const int64_t k = w - it.unit_begin + it.unit_off;
         const int TC = (it.a.ntones + WG - 1) / WG;
         const int64_t nunits = (int64_t)TC * it.a.nout;
         if (k < nunits) {
             const int tc = (int)(k / it.a.nout);
             const int64_t o = k - (int64_t)tc * it.a.nout;
-            const int cnt = (int)min((int64_t)kRun, min(e - w, it.a.nout - o));
+            const int64_t lim = min(e, it.unit_begin + it.units) - w;   // this work-group's and this item's end
+            const int cnt = (int)min((int64_t)kRun, min(lim, it.a.nout - o));
             ddc_run<WG, false>(it.a, tc, o, cnt, lds);
             w += cnt;
         } else {

@@ -118,7 +118,9 @@ hipError_t launch_ddc(const DdcLaunch &a, hipStream_t s);
 
 struct DdcItem {
     DdcLaunch a;
-    int64_t unit_begin;     // first work unit of this item
+    int64_t unit_begin;     // first work unit of this item in the table
+    int64_t unit_off;       // its first unit within the call's units (a chunk of a long call)
+    int64_t units;          // units of this item (the call's last unit is its tail)
 };
 // Threads (= tones per chunk) of the work-group that serves a bank of `ntones`
 // (64 .. 1024, the same rule as the single-stream launch); a grouped launch

@@ -49,6 +49,17 @@ struct Request {
     int stage = -1;            // staging slot holding its copy (host requests, once issued)
 };
 
+struct Done {
+    int stream, slot, stage;
+    int tp = -1, td = -1;      // item tables (PFB, DDC) of a grouped batch, or -1
+    bool reported = false;
+    bool partial = false;      // a chunk of a long DDC call that is not its last: nothing to report
+    Request req;
+    uint64_t pfb_frames, ddc_outputs, ddc_ld;
+    const float *pfb_out, *ddc_out;
+    double t_launch;
+};
+
 struct Stream {
     int id = -1;
     int kinds = 0;
@@ -66,21 +77,40 @@ struct Stream {
     std::vector<uint32_t *> stage_buf;
     std::vector<hipEvent_t> stage_ev;
     std::vector<int> free_stage;
+    // a long DDC call in progress, issued over several batches (grouped modes)
+    struct Chunked {
+        bool on = false;
+        Done d{};
+        rfk::DdcLaunch a{};
+        int64_t units = 0, issued = 0;
+    } ch;
     std::deque<Request> queue;
     int inflight = 0;
     size_t footprint = 0;
     bool closing = false;
 };
 
-struct Done {
-    int stream, slot, stage;
-    int tp = -1, td = -1;      // item tables (PFB, DDC) of a grouped batch, or -1
-    bool reported = false;
-    Request req;
-    uint64_t pfb_frames, ddc_outputs, ddc_ld;
-    const float *pfb_out, *ddc_out;
-    double t_launch;
+
+// What one batch entry launches: the request's PFB part, and which of its DDC
+// units (all, or a chunk); `final` entries complete the request.
+struct Part {
+    bool first = true;                   // the request's first entry (reads its input)
+    bool pfb = false;
+    int64_t ddc_off = 0, ddc_cnt = -1;   // -1: all units
+    bool final = true;
 };
+
+// Work per DDC chunk in tap-tones (about a millisecond at the measured rate):
+// a call with more than two chunks of work is issued over several batches so
+// that light buffers that arrive meanwhile are not queued behind all of it.
+constexpr double kDdcChunkWork = 3.5e9;
+
+int64_t ddc_chunk_units(const rfk::DdcLaunch &a)
+{
+    const double per_unit = (double)rfk::ddc_group_wg(a.ntones) * (double)a.T;
+    const int64_t u = (int64_t)(kDdcChunkWork / per_unit);
+    return u < 1 ? 1 : u;
+}
 
 // Device/pinned layout of one batch's item tables.
 struct Blob {
@@ -308,19 +338,38 @@ int stage_copies(rfs_server *S)
 // mu).  SEQUENTIAL mode takes only the oldest request overall.  A pinned-host
 // request is eligible once its staging copy has been issued.
 bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunch> &pl,
-                std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who)
+                std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who, std::vector<Part> &parts)
 {
+    const bool grouped = S->mode != RFS_MODE_SEQUENTIAL;
     std::vector<Stream *> cand;
     for (auto &kv : S->streams) {
         Stream *s = kv.second;
-        if (!s->queue.empty() && !s->free_slots.empty() && (!s->queue.front().host || s->queue.front().stage >= 0))
+        if (s->ch.on ||
+            (!s->queue.empty() && !s->free_slots.empty() && (!s->queue.front().host || s->queue.front().stage >= 0)))
             cand.push_back(s);
     }
     if (cand.empty()) return false;
-    std::sort(cand.begin(), cand.end(),
-              [](Stream *a, Stream *b) { return a->queue.front().t_submit < b->queue.front().t_submit; });
+    auto t_of = [](Stream *s) { return s->ch.on ? s->ch.d.req.t_submit : s->queue.front().t_submit; };
+    std::sort(cand.begin(), cand.end(), [&](Stream *a, Stream *b) { return t_of(a) < t_of(b); });
     if (S->mode == RFS_MODE_SEQUENTIAL) cand.resize(1);
     for (Stream *s : cand) {
+        if (s->ch.on) {   // the next chunk of a long DDC call
+            Part pt;
+            pt.first = false;
+            pt.ddc_off = s->ch.issued;
+            pt.ddc_cnt = std::min(ddc_chunk_units(s->ch.a), s->ch.units - s->ch.issued);
+            s->ch.issued += pt.ddc_cnt;
+            pt.final = s->ch.issued == s->ch.units;
+            Done d = s->ch.d;
+            d.partial = !pt.final;
+            if (pt.final) s->ch.on = false;
+            out.push_back(d);
+            pl.push_back(rfk::PfbLaunch{});
+            dl.push_back(s->ch.a);
+            who.push_back(s);
+            parts.push_back(pt);
+            continue;
+        }
         Request r = s->queue.front();
         const int slot = s->free_slots.back();
         Done d{};
@@ -362,26 +411,44 @@ bool form_batch(rfs_server *S, std::vector<Done> &out, std::vector<rfk::PfbLaunc
         s->queue.pop_front();
         s->free_slots.pop_back();
         s->inflight++;
+        Part pt;
+        pt.pfb = s->pfb != nullptr;
+        if (grouped && s->ddc && r.n) {
+            const int64_t units = rfk::ddc_group_units(b), cu = ddc_chunk_units(b);
+            if (units > 2 * cu) {   // long call: its first chunk now, the rest in later batches
+                s->ch.on = true;
+                s->ch.d = d;
+                s->ch.a = b;
+                s->ch.units = units;
+                s->ch.issued = cu;
+                pt.ddc_off = 0;
+                pt.ddc_cnt = cu;
+                pt.final = false;
+                d.partial = true;
+            }
+        }
         out.push_back(d);
         pl.push_back(a);
         dl.push_back(b);
         who.push_back(s);
+        parts.push_back(pt);
     }
     return !out.empty();
 }
 
 // Enqueue a batch.  Returns RF_OK or an error (GPU failure).
 int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk::PfbLaunch> &pl,
-                 std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who)
+                 std::vector<rfk::DdcLaunch> &dl, std::vector<Stream *> &who, const std::vector<Part> &parts)
 {
     // the batch reads staged copies: wait for those copies (only)
     for (size_t i = 0; i < who.size(); ++i)
-        if (dn[i].stage >= 0 && hipStreamWaitEvent(S->hs, who[i]->stage_ev[dn[i].stage], 0) != hipSuccess)
+        if (dn[i].stage >= 0 && parts[i].first &&
+            hipStreamWaitEvent(S->hs, who[i]->stage_ev[dn[i].stage], 0) != hipSuccess)
             return set_error(RF_EDEVICE, "wait for staging copy failed");
     // A batch of one request (the common case at light load) gains nothing
     // from item tables, grouped kernels or a graph: it is launched as the
     // single-stream kernels, which compute the same results bit for bit.
-    if (S->mode == RFS_MODE_SEQUENTIAL || who.size() == 1) {
+    if (S->mode == RFS_MODE_SEQUENTIAL || (who.size() == 1 && parts[0].ddc_cnt < 0)) {
         for (size_t i = 0; i < who.size(); ++i) {
             Stream *s = who[i];
             if (s->pfb && dn[i].req.n) {
@@ -407,7 +474,7 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
     for (size_t i = 0; i < who.size(); ++i) {
         Stream *s = who[i];
         if (!dn[i].req.n) continue;
-        if (s->pfb) {
+        if (parts[i].pfb) {
             const int t = class_index(S, s->N, s->M);
             rfk::GroupHeader *h = hdr_at(b.host, S->region, t);
             rfk::PfbItem &it = items_at<rfk::PfbItem>(b.host, S->region, t)[h->count];
@@ -425,7 +492,9 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
             rfk::DdcItem &it = items_at<rfk::DdcItem>(b.host, S->region, t)[h->count];
             it.a = dl[i];
             it.unit_begin = h->total;
-            h->total += rfk::ddc_group_units(dl[i]);
+            it.unit_off = parts[i].ddc_off;
+            it.units = parts[i].ddc_cnt < 0 ? rfk::ddc_group_units(dl[i]) : parts[i].ddc_cnt;
+            h->total += it.units;
             h->count++;
             dn[i].td = t;
         }
@@ -471,8 +540,8 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
     for (size_t i = 0; i < who.size(); ++i) {
         Stream *s = who[i];
         if (!dn[i].req.n) continue;
-        if (s->pfb) rfi::pfb_commit(s->pfb, pl[i], dn[i].req.n, dn[i].pfb_frames, S->hs);
-        if (s->ddc) rfi::ddc_commit(s->ddc, dn[i].req.n, S->hs);
+        if (parts[i].pfb) rfi::pfb_commit(s->pfb, pl[i], dn[i].req.n, dn[i].pfb_frames, S->hs);
+        if (s->ddc && parts[i].final) rfi::ddc_commit(s->ddc, dn[i].req.n, S->hs);
     }
     return RF_OK;
 }
@@ -511,7 +580,7 @@ void report_early(rfs_server *S, Blob &b)
     bool any = false;
     double t = 0;
     for (Done &d : b.done) {
-        if (d.reported || (d.tp < 0 && d.td < 0)) continue;
+        if (d.reported || d.partial || (d.tp < 0 && d.td < 0)) continue;
         if (d.tp >= 0 && hipEventQuery(b.tev[d.tp]) != hipSuccess) continue;
         if (d.td >= 0 && hipEventQuery(b.tev[d.td]) != hipSuccess) continue;
         if (!any) {
@@ -529,7 +598,7 @@ void finish_blob(rfs_server *S, Blob &b)
     const double t = now_s();
     std::lock_guard<std::mutex> lk(S->mu);
     for (Done &d : b.done)
-        if (!d.reported) report(S, d, t);
+        if (!d.reported && !d.partial) report(S, d, t);
     S->st.batches++;
     S->st.gpu_busy_seconds += t - b.t_launch;
     b.done.clear();
@@ -544,6 +613,7 @@ void scheduler(rfs_server *S)
     std::vector<rfk::PfbLaunch> pl;
     std::vector<rfk::DdcLaunch> dl;
     std::vector<Stream *> who;
+    std::vector<Part> parts;
     while (true) {
         // retire finished batches, oldest first
         for (int k = 0; k < 2; ++k) {
@@ -561,11 +631,12 @@ void scheduler(rfs_server *S)
         pl.clear();
         dl.clear();
         who.clear();
+        parts.clear();
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (S->stop && S->blobs[0].busy == false && S->blobs[1].busy == false) {
                 bool pending = false;
-                for (auto &kv : S->streams) pending |= !kv.second->queue.empty();
+                for (auto &kv : S->streams) pending |= !kv.second->queue.empty() || kv.second->ch.on;
                 if (!pending) break;
             }
             if (stage_copies(S)) {
@@ -573,7 +644,7 @@ void scheduler(rfs_server *S)
                 S->stop = true;
                 break;
             }
-            if (!form_batch(S, dn, pl, dl, who)) {
+            if (!form_batch(S, dn, pl, dl, who, parts)) {
                 const bool any_busy = S->blobs[0].busy || S->blobs[1].busy;
                 if (S->stop && !any_busy) break;
                 if (any_busy) {
@@ -584,7 +655,7 @@ void scheduler(rfs_server *S)
                 }
                 continue;
             }
-            int rc = launch_batch(S, b, dn, pl, dl, who);
+            int rc = launch_batch(S, b, dn, pl, dl, who, parts);
             if (rc) {
                 S->fatal = rf_last_error();
                 for (Stream *s : who) s->inflight--;
