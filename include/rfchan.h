@@ -355,7 +355,7 @@ typedef struct rfs_server *rfs_t;
 
 #define RFS_MODE_SEQUENTIAL 0 /* one plain kernel per request, in arrival order (baseline) */
 #define RFS_MODE_BATCHED 1    /* grouped persistent kernels, launched directly per batch */
-#define RFS_MODE_GRAPH 2      /* grouped persistent kernels, replayed from captured hipGraphs */
+#define RFS_MODE_GRAPH 2      /* grouped persistent kernels, replayed from prebuilt hipGraphs */
 
 typedef struct {
     int32_t kinds;            /* RFS_PFB and/or RFS_DDC */

@@ -248,6 +248,18 @@ int64_t ddc_group_units(const DdcLaunch &a)
     return (int64_t)TC * a.nout + 1;
 }
 
+const void *ddc_group_kernel(int wg)
+{
+    switch (wg) {
+    case 64: return reinterpret_cast<const void *>(&ddc_group<64>);
+    case 128: return reinterpret_cast<const void *>(&ddc_group<128>);
+    case 256: return reinterpret_cast<const void *>(&ddc_group<256>);
+    case 512: return reinterpret_cast<const void *>(&ddc_group<512>);
+    case 1024: return reinterpret_cast<const void *>(&ddc_group<1024>);
+    default: return nullptr;
+    }
+}
+
 hipError_t launch_ddc_group(int wg, const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s)
 {
     if (grid < 1) return hipErrorInvalidValue;

@@ -786,6 +786,31 @@ hipError_t launch_pfb_group_n(int M, const GroupHeader *hdr, const PfbItem *item
     }
 }
 
+// The grouped kernel for (N, M), as a function pointer (for graph kernel nodes).
+template <int N>
+const void *pfb_group_fn(int M)
+{
+    switch (M) {
+    case 1: return reinterpret_cast<const void *>(&pfb_group<N, 1>);
+    case 2: return reinterpret_cast<const void *>(&pfb_group<N, 2>);
+    case 3: return reinterpret_cast<const void *>(&pfb_group<N, 3>);
+    case 4: return reinterpret_cast<const void *>(&pfb_group<N, 4>);
+    case 5: return reinterpret_cast<const void *>(&pfb_group<N, 5>);
+    case 6: return reinterpret_cast<const void *>(&pfb_group<N, 6>);
+    case 7: return reinterpret_cast<const void *>(&pfb_group<N, 7>);
+    case 8: return reinterpret_cast<const void *>(&pfb_group<N, 8>);
+    case 9: return reinterpret_cast<const void *>(&pfb_group<N, 9>);
+    case 10: return reinterpret_cast<const void *>(&pfb_group<N, 10>);
+    case 11: return reinterpret_cast<const void *>(&pfb_group<N, 11>);
+    case 12: return reinterpret_cast<const void *>(&pfb_group<N, 12>);
+    case 13: return reinterpret_cast<const void *>(&pfb_group<N, 13>);
+    case 14: return reinterpret_cast<const void *>(&pfb_group<N, 14>);
+    case 15: return reinterpret_cast<const void *>(&pfb_group<N, 15>);
+    case 16: return reinterpret_cast<const void *>(&pfb_group<N, 16>);
+    default: return nullptr;
+    }
+}
+
 // Dispatch over M (1..16) for a fixed N with the default variant.
 template <int N, int V>
 hipError_t launch_pfb_nv(const PfbLaunch &a, hipStream_t s)
@@ -812,7 +837,8 @@ hipError_t launch_pfb_nv(const PfbLaunch &a, hipStream_t s)
 }
 
 // Per-N entry points, each defined in its own translation unit.
-#define RF_DECL_GROUP(n) hipError_t launch_pfb_group_n##n(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s);
+#define RF_DECL_GROUP(n) hipError_t launch_pfb_group_n##n(int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s); \
+    const void *pfb_group_fn_n##n(int M);
 RF_DECL_GROUP(16) RF_DECL_GROUP(32) RF_DECL_GROUP(64) RF_DECL_GROUP(128) RF_DECL_GROUP(256)
 RF_DECL_GROUP(512) RF_DECL_GROUP(1024) RF_DECL_GROUP(2048) RF_DECL_GROUP(4096)
 #undef RF_DECL_GROUP

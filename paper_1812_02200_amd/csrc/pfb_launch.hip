@@ -117,6 +117,22 @@ int pfb_group_wg_size(int N)
     }
 }
 
+const void *pfb_group_kernel(int N, int M)
+{
+    switch (N) {
+    case 16: return pfb_group_fn_n16(M);
+    case 32: return pfb_group_fn_n32(M);
+    case 64: return pfb_group_fn_n64(M);
+    case 128: return pfb_group_fn_n128(M);
+    case 256: return pfb_group_fn_n256(M);
+    case 512: return pfb_group_fn_n512(M);
+    case 1024: return pfb_group_fn_n1024(M);
+    case 2048: return pfb_group_fn_n2048(M);
+    case 4096: return pfb_group_fn_n4096(M);
+    default: return nullptr;
+    }
+}
+
 hipError_t launch_pfb_group(int N, int M, const GroupHeader *hdr, const PfbItem *items, int grid, hipStream_t s)
 {
     if (grid < 1) return hipErrorInvalidValue;

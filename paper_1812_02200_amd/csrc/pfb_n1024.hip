@@ -31,4 +31,9 @@ hipError_t launch_pfb_group_n1024(int M, const GroupHeader *hdr, const PfbItem *
     return launch_pfb_group_n<1024>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n1024(int M)
+{
+    return pfb_group_fn<1024>(M);
+}
+
 }  // namespace rfk

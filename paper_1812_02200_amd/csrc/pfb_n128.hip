@@ -15,4 +15,9 @@ hipError_t launch_pfb_group_n128(int M, const GroupHeader *hdr, const PfbItem *i
     return launch_pfb_group_n<128>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n128(int M)
+{
+    return pfb_group_fn<128>(M);
+}
+
 }  // namespace rfk

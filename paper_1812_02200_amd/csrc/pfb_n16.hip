@@ -15,4 +15,9 @@ hipError_t launch_pfb_group_n16(int M, const GroupHeader *hdr, const PfbItem *it
     return launch_pfb_group_n<16>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n16(int M)
+{
+    return pfb_group_fn<16>(M);
+}
+
 }  // namespace rfk

@@ -17,4 +17,9 @@ hipError_t launch_pfb_group_n2048(int M, const GroupHeader *hdr, const PfbItem *
     return launch_pfb_group_n<2048>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n2048(int M)
+{
+    return pfb_group_fn<2048>(M);
+}
+
 }  // namespace rfk

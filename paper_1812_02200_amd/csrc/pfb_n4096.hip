@@ -15,4 +15,9 @@ hipError_t launch_pfb_group_n4096(int M, const GroupHeader *hdr, const PfbItem *
     return launch_pfb_group_n<4096>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n4096(int M)
+{
+    return pfb_group_fn<4096>(M);
+}
+
 }  // namespace rfk

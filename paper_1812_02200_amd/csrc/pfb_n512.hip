@@ -17,4 +17,9 @@ hipError_t launch_pfb_group_n512(int M, const GroupHeader *hdr, const PfbItem *i
     return launch_pfb_group_n<512>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n512(int M)
+{
+    return pfb_group_fn<512>(M);
+}
+
 }  // namespace rfk

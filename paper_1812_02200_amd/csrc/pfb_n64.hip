@@ -15,4 +15,9 @@ hipError_t launch_pfb_group_n64(int M, const GroupHeader *hdr, const PfbItem *it
     return launch_pfb_group_n<64>(M, hdr, items, grid, s);
 }
 
+const void *pfb_group_fn_n64(int M)
+{
+    return pfb_group_fn<64>(M);
+}
+
 }  // namespace rfk

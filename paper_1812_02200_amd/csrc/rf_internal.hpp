@@ -129,6 +129,9 @@ int ddc_group_wg(int ntones);
 // Work units of one item in a grouped launch: (tone chunk, output) pairs + 1 tail.
 int64_t ddc_group_units(const DdcLaunch &a);
 hipError_t launch_ddc_group(int wg, const GroupHeader *hdr, const DdcItem *items, int grid, hipStream_t s);
+// The grouped kernels as function pointers (graph kernel nodes), or null.
+const void *ddc_group_kernel(int wg);
+const void *pfb_group_kernel(int N, int M);
 int ddc_default_grid(int ntones, int64_t nout);
 
 // Number of float entries of the half-wave sine table.

@@ -139,7 +139,7 @@ struct rfs_server {
     uint64_t budget = 0, admitted = 0;
     hipStream_t hs = nullptr;
     hipStream_t cs = nullptr;          // host-to-device copies of pinned-host buffers
-    std::vector<hipStream_t> branch;   // fork streams for graph capture
+    std::vector<hipStream_t> branch;   // branch streams of the batched mode's grouped launches
     std::vector<hipEvent_t> fork_ev;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -258,10 +258,14 @@ void rebuild_classes(rfs_server *S)
 
 int pfb_grid(rfs_server *S, int N) { return N >= 2048 ? S->cus : 2 * S->cus; }
 
-// Capture the batch graph for the current class lists into blob b:
-// upload tables, then fork: one grouped kernel per PFB class and per DDC class
-// on parallel branches, join.
-int capture_graph(rfs_server *S, Blob &b)
+// Build the batch graph for the current class lists into blob b: a table
+// upload node, then one grouped-kernel node per PFB class and per DDC class
+// (each depending on the upload only, so they may run side by side), each
+// followed by an event-record node for that table.  The graph is assembled
+// node by node rather than captured from a stream: a capture in progress on
+// the scheduler's thread would make device-wide synchronisation in client
+// threads fail.
+int build_graph(rfs_server *S, Blob &b)
 {
     if (b.exec) {
         (void)hipGraphExecDestroy(b.exec);
@@ -273,40 +277,49 @@ int capture_graph(rfs_server *S, Blob &b)
     }
     const int C = (int)S->classes.size();
     const int NT = C + (int)S->ddc_classes.size();
-    hipError_t e = hipStreamBeginCapture(S->hs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return set_error(RF_EDEVICE, "hipStreamBeginCapture failed");
-    hipError_t err = hipMemcpyAsync(b.dev, b.host, S->region * NT, hipMemcpyHostToDevice, S->hs);
-    if (err == hipSuccess) err = hipEventRecord(S->fork_ev[0], S->hs);
-    for (int t = 0; t < NT && err == hipSuccess; ++t) {
-        hipStream_t bs = S->branch[t % kMaxBranches];
-        err = hipStreamWaitEvent(bs, S->fork_ev[0], 0);
-        if (err != hipSuccess) break;
-        const rfk::GroupHeader *h = hdr_at(b.dev, S->region, t);
-        if (t < C)
-            err = rfk::launch_pfb_group(S->classes[t].first, S->classes[t].second, h,
-                                        items_at<rfk::PfbItem>(b.dev, S->region, t),
-                                        pfb_grid(S, S->classes[t].first), bs);
-        else
-            err = rfk::launch_ddc_group(S->ddc_classes[t - C], h, items_at<rfk::DdcItem>(b.dev, S->region, t),
-                                        S->cus, bs);
-        if (err == hipSuccess) err = hipEventRecord(b.tev[t], bs);
-    }
-    const int used = std::min(NT, kMaxBranches);   // join only the branches the capture forked
-    for (int k = 0; k < used && err == hipSuccess; ++k) {
-        err = hipEventRecord(S->fork_ev[1 + k], S->branch[k]);
-        if (err == hipSuccess) err = hipStreamWaitEvent(S->hs, S->fork_ev[1 + k], 0);
-    }
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(S->hs, &g);
-    if (err != hipSuccess || e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
-        return set_error(RF_EDEVICE, "graph capture of the batch failed");
+    hipError_t err = hipGraphCreate(&g, 0);
+    hipGraphNode_t up = nullptr;
+    if (err == hipSuccess)
+        err = hipGraphAddMemcpyNode1D(&up, g, nullptr, 0, b.dev, b.host, S->region * NT, hipMemcpyHostToDevice);
+    for (int t = 0; t < NT && err == hipSuccess; ++t) {
+        const rfk::GroupHeader *h = hdr_at(b.dev, S->region, t);
+        const void *fn;
+        int grid, block;
+        const void *items;
+        if (t < C) {
+            fn = rfk::pfb_group_kernel(S->classes[t].first, S->classes[t].second);
+            grid = pfb_grid(S, S->classes[t].first);
+            block = rfk::pfb_group_wg_size(S->classes[t].first);
+            items = items_at<rfk::PfbItem>(b.dev, S->region, t);
+        } else {
+            fn = rfk::ddc_group_kernel(S->ddc_classes[t - C]);
+            grid = S->cus;
+            block = S->ddc_classes[t - C];
+            items = items_at<rfk::DdcItem>(b.dev, S->region, t);
+        }
+        if (!fn) {
+            err = hipErrorInvalidValue;
+            break;
+        }
+        void *args[] = {(void *)&h, (void *)&items};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(fn);
+        kp.gridDim = dim3((unsigned)grid);
+        kp.blockDim = dim3((unsigned)block);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t kn = nullptr, en = nullptr;
+        err = hipGraphAddKernelNode(&kn, g, &up, 1, &kp);
+        if (err == hipSuccess) err = hipGraphAddEventRecordNode(&en, g, &kn, 1, b.tev[t]);
     }
-    e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return set_error(RF_EDEVICE, "hipGraphInstantiate failed");
+    if (err == hipSuccess) err = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        b.exec = nullptr;
+        (void)hipGetLastError();
+        return set_error(RF_EDEVICE, "building the batch graph failed");
     }
     b.graph = g;
     b.graph_version = S->class_version;
@@ -501,14 +514,14 @@ int launch_batch(rfs_server *S, Blob &b, std::vector<Done> &dn, std::vector<rfk:
     }
     if (S->mode == RFS_MODE_GRAPH) {
         if (b.graph_version != S->class_version) {
-            int rc = capture_graph(S, b);
+            int rc = build_graph(S, b);
             if (rc) return rc;
         }
         if (hipGraphLaunch(b.exec, S->hs) != hipSuccess) return set_error(RF_EDEVICE, "hipGraphLaunch failed");
     } else {
         hipError_t e = hipMemcpyAsync(b.dev, b.host, S->region * NT, hipMemcpyHostToDevice, S->hs);
         if (e != hipSuccess) return set_error(RF_EDEVICE, "table upload failed");
-        // the captured graph's topology, launched directly: table t on branch
+        // the batch graph's topology, launched directly: table t on branch
         // t mod kMaxBranches (empty tables skipped), then join
         e = hipEventRecord(S->fork_ev[0], S->hs);
         int used = 0;

@@ -259,3 +259,43 @@ def test_serve_served_mix_shape_equals_alone():
                 assert np.array_equal(g["ddc"].view(np.uint64), yd.view(np.uint64)), s
         del p, d
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["batched", "graph"])
+def test_serve_long_ddc_call_in_chunks_equals_alone(mode):
+    """A DDC call long enough to be issued in chunks over several batches
+    (1024 tones, 1024 taps, 2^23 samples: three chunks), interleaved with light
+    PFB buffers of another stream, equals the same calls made alone, bit for
+    bit; the stream's state carries on to its next call."""
+    rf = _rf()
+    import torch
+
+    from paper_1812_02200_amd import serve
+    rng = np.random.default_rng(31)
+    heavy = dict(N=256, M=4, h=siggen.pfb_prototype(256, 4, "kaiser", 9.0),
+                 ddc=(siggen.random_words(rng, 1024), siggen.random_words(rng, 1024),
+                      siggen.ddc_lowpass(1024, 80e3, siggen.FS, "blackman"), 1000))
+    light = dict(N=1024, M=8, h=siggen.pfb_prototype(1024, 8, "kaiser", 9.0), ddc=None)
+    specs = [heavy, light]
+    sizes = [[1 << 23, 1 << 18, 1 << 23], [1 << 16] * 6]
+    pool_n = 1 << 25
+    pool = siggen.iq_torch(siggen.StreamSpec(37, siggen.pfb_small().stream.tones, 300.0), 0, pool_n)
+    mix_specs, arrivals = _mix_arrivals(specs, sizes, pool_n, seed=9)
+    m = {"batched": rf.RFS_MODE_BATCHED, "graph": rf.RFS_MODE_GRAPH}[mode]
+    res = serve.run(mix_specs, arrivals, pool, m, budget=16 << 30, realtime=False, collect=True)
+    log("long DDC call (%s): %d requests in %s batches" % (mode, len(arrivals), res.get("batches")))
+    for s, sp in enumerate(specs):
+        p = rf.Pfb(sp["N"], sp["M"], sp["h"], max_samples_per_call=max(sizes[s]))
+        d = None
+        if sp["ddc"] is not None:
+            w, p0, lpf, D = sp["ddc"]
+            d = rf.Ddc(w, lpf, D, p0, max_samples_per_call=max(sizes[s]))
+        got = res["outputs"][s]
+        bufs = [a for a in arrivals if a.stream == s]
+        assert len(got) == len(bufs)
+        for g, a in zip(got, bufs):
+            b = pool[2 * a.pool_start: 2 * (a.pool_start + a.nsamples)]
+            assert np.array_equal(g["pfb"].view(np.uint64), p.process(b).cpu().numpy().view(np.uint64)), s
+            if d is not None:
+                assert np.array_equal(g["ddc"].view(np.uint64), d.process(b).cpu().numpy().view(np.uint64)), s
+    torch.cuda.synchronize()
