@@ -12,15 +12,17 @@
 //    (C = 4 columns per thread; 8 for N = 4096, whose lane group is then a
 //    512-thread work-group with 256 registers per thread instead of a
 //    1024-thread one with 128).  Thread c of an LG owns the C columns
-//    n = c + k*L (k < C), holds their M taps and a window of M+3 blocks of
-//    input in registers, and produces four frames per phase.  Its C FIR
-//    outputs are exactly the inputs of one radix-C butterfly of the first
-//    Stockham pass (stride N/C, no twiddles), which it computes before
+//    n = c + k*L (k < C), holds their M taps (for C = 8: in LDS or read
+//    through the caches) and a window of M+FP-1 blocks of input in
+//    registers, and produces FP frames per phase (4; 2 for C = 8).  Its C
+//    FIR outputs are exactly the inputs of one radix-C butterfly of the
+//    first Stockham pass (stride N/C, no twiddles), which it computes before
 //    writing to LDS.
 //  * The remaining passes are radix-16 (radix 8/4/2 for the last one) Stockham
 //    passes: a team of N/16 threads owns one frame, every thread holds 16
-//    points (or more, in several butterflies) per pass.  With C = 8 a phase
-//    has two frames, so the 512 threads are again one team per frame.  The last pass writes the natural-order spectrum straight to HBM
+//    points (or more, in several butterflies) per pass; the FP frames of a
+//    phase buffer take the whole work-group.  The last pass writes the
+//    natural-order spectrum straight to HBM
 //    -- or, when the caller chose a set of channels, back to LDS, from where
 //    the frame's team gathers the chosen bins into consecutive columns (same
 //    arithmetic, fewer bytes written).
