@@ -261,7 +261,7 @@ def test_serve_served_mix_shape_equals_alone():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("mode", ["batched", "graph"])
+@pytest.mark.parametrize("mode", ["batched", "graph", "graph_host"])
 def test_serve_long_ddc_call_in_chunks_equals_alone(mode):
     """A DDC call long enough to be issued in chunks over several batches
     (1024 tones, 1024 taps, 2^23 samples: three chunks), interleaved with light
@@ -281,8 +281,15 @@ def test_serve_long_ddc_call_in_chunks_equals_alone(mode):
     pool_n = 1 << 25
     pool = siggen.iq_torch(siggen.StreamSpec(37, siggen.pfb_small().stream.tones, 300.0), 0, pool_n)
     mix_specs, arrivals = _mix_arrivals(specs, sizes, pool_n, seed=9)
-    m = {"batched": rf.RFS_MODE_BATCHED, "graph": rf.RFS_MODE_GRAPH}[mode]
-    res = serve.run(mix_specs, arrivals, pool, m, budget=16 << 30, realtime=False, collect=True)
+    m = {"batched": rf.RFS_MODE_BATCHED, "graph": rf.RFS_MODE_GRAPH, "graph_host": rf.RFS_MODE_GRAPH}[mode]
+    src, host_slots = pool, 0
+    if mode == "graph_host":   # the same buffers from pinned host memory, staged by the server
+        src = torch.empty(pool.shape, dtype=pool.dtype, pin_memory=True)
+        src.copy_(pool)
+        torch.cuda.synchronize()
+        host_slots = 2
+    res = serve.run(mix_specs, arrivals, src, m, budget=16 << 30, realtime=False, collect=True,
+                    host_slots=host_slots)
     log("long DDC call (%s): %d requests in %s batches" % (mode, len(arrivals), res.get("batches")))
     for s, sp in enumerate(specs):
         p = rf.Pfb(sp["N"], sp["M"], sp["h"], max_samples_per_call=max(sizes[s]))
