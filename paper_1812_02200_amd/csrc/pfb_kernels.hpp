@@ -287,8 +287,10 @@ struct WinT<true> {
 };
 
 // Eight columns per thread (N = 4096): M x 8 taps would not fit beside the
-// window.  The handle stores a per-thread copy [c][m][k] (the taps of thread
-// c's columns for tap m) after the natural [m N + n] layout.  For M <= 4 each
+// window.  The handle stores a copy [m][q][c][4] (tap m of thread c's
+// columns 4q .. 4q+3, 16 bytes; consecutive threads at consecutive 16-byte
+// slots, so one wave's row read is 1 KiB contiguous) after the natural
+// [m N + n] layout.  For M <= 4 each
 // thread copies its rows into LDS (64 KiB at most, read only by that thread);
 // otherwise every phase reads them from that copy, through the caches (all
 // work-groups of an XCD read the same taps).  (Measured: splitting larger M
@@ -313,8 +315,8 @@ struct FirState {
     static constexpr int FP = pfb_frames_per_phase(N);
     static constexpr int W = M + FP - 1;   // window blocks fp .. fp+M+FP-2
     float hr[TapsInMemory<N>::ON ? 1 : M][C];
-    const RF_GLOBAL f4v *tp;          // TapsInMemory: this thread's [m] rows of C taps
-    const f4v *tl;                    // TapsInMemory: its LDS rows, row m at tl[2 m L]
+    const RF_GLOBAL f4v *tp;          // TapsInMemory: row m, part q of this thread's taps at tp[(2 m + q) L]
+    const f4v *tl;                    // TapsInMemory: the same in LDS
     WinT<PACKED> xw[W][C];
 };
 
@@ -339,7 +341,7 @@ __device__ __forceinline__ void fir_phase(const FirState<N, M> &st, cf *lds, int
             float t[C];
 #pragma unroll
             for (int q = 0; q < C / 4; ++q) {
-                const f4v t4 = m < TT::LR ? st.tl[(m * (C / 4) + q) * L] : st.tp[m * (C / 4) + q];
+                const f4v t4 = m < TT::LR ? st.tl[(m * (C / 4) + q) * L] : st.tp[(m * (C / 4) + q) * L];
                 t[4 * q] = t4.x;
                 t[4 * q + 1] = t4.y;
                 t[4 * q + 2] = t4.z;
@@ -534,12 +536,12 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     FirState<N, M> st;
     if constexpr (TapsInMemory<N>::ON) {
         using TT = TapTiers<N, M>;
-        st.tp = reinterpret_cast<const RF_GLOBAL f4v *>(gptr(a.taps) + (size_t)N * M) + (size_t)c * M * (C / 4);
+        st.tp = reinterpret_cast<const RF_GLOBAL f4v *>(gptr(a.taps) + (size_t)N * M) + c;
         st.tl = sh.taps + c;
 #pragma unroll
         for (int m = 0; m < TT::LR; ++m)
 #pragma unroll
-            for (int q = 0; q < C / 4; ++q) sh.taps[(m * (C / 4) + q) * L + c] = st.tp[m * (C / 4) + q];
+            for (int q = 0; q < C / 4; ++q) sh.taps[(m * (C / 4) + q) * L + c] = st.tp[(m * (C / 4) + q) * L];
     } else {
 #pragma unroll
         for (int m = 0; m < M; ++m)

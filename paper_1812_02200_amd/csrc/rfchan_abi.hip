@@ -353,8 +353,8 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         return fail(RF_ENOMEM, "pfb_create: host allocation");
     }
     // Eight columns per thread (N = 4096): the natural layout is followed by a
-    // per-thread copy [c][m][k] = h[m N + c + k N/8] that the kernel reads a
-    // row of eight taps at a time
+    // copy [m][q][c][k] = h[m N + c + (4q + k) N/8] that the kernel reads as
+    // 16-byte parts, consecutive threads at consecutive parts
     const int fir_c = rfk::pfb_fir_radix(nchan);
     const size_t ntaps_dev = fir_c == 8 && dft_mode == RF_DFT_FFT_F32 ? 2 * span : span;
     float *taps = (float *)malloc(sizeof(float) * ntaps_dev);
@@ -368,10 +368,12 @@ int pfb_create(rf_pfb_t *out, int32_t nchan, int32_t ntaps, const float *proto, 
         memcpy(taps, proto, sizeof(float) * span);
         if (ntaps_dev > span) {
             const int L = nchan / fir_c;
-            for (int c = 0; c < L; ++c)
-                for (int m = 0; m < ntaps; ++m)
-                    for (int k = 0; k < fir_c; ++k)
-                        taps[span + ((size_t)c * ntaps + m) * fir_c + k] = proto[(size_t)m * nchan + c + k * L];
+            for (int m = 0; m < ntaps; ++m)
+                for (int q = 0; q < fir_c / 4; ++q)
+                    for (int c = 0; c < L; ++c)
+                        for (int k = 0; k < 4; ++k)
+                            taps[span + (((size_t)m * (fir_c / 4) + q) * L + c) * 4 + k] =
+                                proto[(size_t)m * nchan + c + (4 * q + k) * L];
         }
     } else {
         rfk::pfb_mfma_table_fill(nchan, mfma_exp, tw);
