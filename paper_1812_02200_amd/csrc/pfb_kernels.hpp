@@ -497,6 +497,12 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
     // loaded non-temporally, so they do not displace shared blocks in the L2
     // (measured 2-3 us faster per 2^24-sample launch at N = 1024, M = 8).
     constexpr bool PRE_AFTER = TapsInMemory<N>::ON;
+    // Short runs of small frames (N <= 64: tuned runs of 8 to 16 frames
+    // against M-1 shared blocks at each edge) keep the shared edge blocks in
+    // ordinary loads (N = 16, M = 8: 57 -> 51 us per 2^24 samples); from
+    // N = 128 on, streaming every prefetched block measured as fast or faster
+    // (N = 1024: 45 against 48 us).
+    constexpr bool EDGE_CACHED = N <= 64;
     cf *lds_all = sh.frames;
     cf *twl = sh.tw;
 
@@ -582,10 +588,25 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
                 auto prefetch = [&]() __attribute__((always_inline)) {
                     if (more) {
                         const RF_GLOBAL uint32_t *p = (base - c) + phase_local<RELOAD>(c) + (int64_t)(back ? FP * ph - FP : FP * ph + W) * N;
+                        // blocks read by this run only stream; with EDGE_CACHED the
+                        // blocks it shares with the neighbouring run (within M-1
+                        // of the run's edge) stay cached
+                        auto stream = [&]() __attribute__((always_inline)) {
 #pragma unroll
-                        for (int i = 0; i < FP; ++i)
+                            for (int i = 0; i < FP; ++i)
 #pragma unroll
-                            for (int k = 0; k < C; ++k) pre[i][k] = __builtin_nontemporal_load(&p[i * N + k * L]);
+                                for (int k = 0; k < C; ++k) pre[i][k] = __builtin_nontemporal_load(&p[i * N + k * L]);
+                        };
+                        if constexpr (!EDGE_CACHED) {
+                            stream();
+                        } else if (back ? FP * ph - FP >= M - 1 : FP * ph + W + FP <= RL) {
+                            stream();
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < FP; ++i)
+#pragma unroll
+                                for (int k = 0; k < C; ++k) pre[i][k] = p[i * N + k * L];
+                        }
                     }
                 };
                 if constexpr (!PRE_AFTER) prefetch();
@@ -632,10 +653,22 @@ __device__ __forceinline__ void pfb_body(const PfbLaunch &a, int lwg, int G, Pfb
             auto prefetch = [&]() __attribute__((always_inline)) {
                 if (more) {
                     const RF_GLOBAL uint32_t *p = (base - c) + phase_local<RELOAD>(c) + (int64_t)(FP * ph + W) * N;
+                    auto stream = [&]() __attribute__((always_inline)) {   // blocks read by this run only
 #pragma unroll
-                    for (int i = 0; i < FP; ++i)
+                        for (int i = 0; i < FP; ++i)
 #pragma unroll
-                        for (int k = 0; k < C; ++k) pre[i][k] = __builtin_nontemporal_load(&p[i * N + k * L]);
+                            for (int k = 0; k < C; ++k) pre[i][k] = __builtin_nontemporal_load(&p[i * N + k * L]);
+                    };
+                    if constexpr (!EDGE_CACHED) {
+                        stream();
+                    } else if (FP * ph + W + FP <= RL) {
+                        stream();
+                    } else {                        // shared with the next run: keep them cached
+#pragma unroll
+                        for (int i = 0; i < FP; ++i)
+#pragma unroll
+                            for (int k = 0; k < C; ++k) pre[i][k] = p[i * N + k * L];
+                    }
                 }
             };
             if constexpr (!PRE_AFTER) prefetch();
