@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 import siggen
-from gpu_util import err_fs, err_rel, f32, log, need_gpu, run_pfb, to_dev
+from gpu_util import check_pfb_elements, err_fs, err_rel, f32, log, need_gpu, run_pfb, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -53,8 +53,9 @@ def tone_bins_of_words(words, N):
     return np.unique(np.rint(w.astype(np.float64) / 2.0 ** 64 * N).astype(np.int64) % N)
 
 
-def check(y, ref, h, tone_bins, label):
-    """Whole-frame bars plus the tone / quiet-bin split; logs every figure."""
+def check(y, ref, h, tone_bins, label, iq):
+    """Whole-frame bars, the tone / quiet-bin split and the per-bin FP32 bound;
+    logs every figure."""
     assert y.shape == ref.shape, (y.shape, ref.shape)
     N = ref.shape[1]
     e, r = err_fs(y, ref, h.sum()), err_rel(y, ref)
@@ -70,6 +71,7 @@ def check(y, ref, h, tone_bins, label):
     assert r <= TOL_REL
     assert r_tone <= TOL_REL
     assert r_quiet <= TOL_REL
+    check_pfb_elements(y, ref, h, N, h.size // N, iq)
 
 
 @pytest.mark.parametrize("N,M", [(60, 4), (100, 1), (1000, 8), (1536, 2), (3000, 3)])
@@ -82,7 +84,7 @@ def test_one_step_non_power_of_two_full(N, M):
     log("large one-step N=%d M=%d" % (N, M))
     y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), to_dev(iq), [n], torch)
     ref = oracle.pfb(f32(h), N, M, iq=iq)
-    check(y, ref, h, ks, "one-step N=%d M=%d" % (N, M))
+    check(y, ref, h, ks, "one-step N=%d M=%d" % (N, M), iq)
 
 
 @pytest.mark.parametrize("N,M", [(8192, 4), (6000, 2), (100000, 8), (65536, 2), (1 << 20, 1), (12000, 12)])
@@ -96,7 +98,7 @@ def test_four_step(N, M):
     y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), to_dev(iq), [n], torch)
     assert y.shape[0] == oracle.pfb_nframes(n, N, M)
     ref = oracle.pfb_fold_fft(f32(h), N, M, iq=iq)
-    check(y, ref, h, ks, "four-step N=%d M=%d" % (N, M))
+    check(y, ref, h, ks, "four-step N=%d M=%d" % (N, M), iq)
 
 
 def test_large_splits_bit_identical():
@@ -130,7 +132,7 @@ def test_ten_million_channels():
     y = run_pfb(rf.Pfb(N, M, h, max_samples_per_call=n), to_dev(iq), [n], torch)
     assert y.shape == (2, N)
     ref = oracle.pfb_fold_fft(f32(h), N, M, iq=iq)
-    check(y, ref, h, ks, "N=10^7 M=2")
+    check(y, ref, h, ks, "N=10^7 M=2", iq)
 
 
 def test_fig3_shape_production_stream():
@@ -151,7 +153,7 @@ def test_fig3_shape_production_stream():
     iq = d.cpu().numpy()
     assert y.shape[0] == oracle.pfb_nframes(2 * buf, N, M)
     ref = oracle.pfb_fold_fft(f32(h), N, M, iq=iq)
-    check(y, ref, h, tone_bins_of_words(w.stream.tones.words, N), "fig3 production N=10^5 M=8")
+    check(y, ref, h, tone_bins_of_words(w.stream.tones.words, N), "fig3 production N=10^5 M=8", iq)
 
 
 def test_small_non_power_of_two_with_many_frames():

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import siggen
-from gpu_util import err_fs, err_rel, f32, log, need_gpu, run_pfb, to_dev
+from gpu_util import check_pfb_elements, err_fs, err_rel, f32, log, need_gpu, run_pfb, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +38,7 @@ def test_pfb_small_workload_parity():
     e, r = err_fs(y, ref, w.h.sum()), err_rel(y, ref)
     log("err_fs=%.3g err_rel=%.3g" % (e, r))
     assert e <= TOL_FS and r <= TOL_REL
+    check_pfb_elements(y, ref, w.h, w.N, w.M, iq)
 
 
 SHAPES = [(16, 1), (16, 4), (32, 3), (64, 2), (64, 8), (128, 5), (256, 8), (256, 16),
@@ -63,6 +64,7 @@ def test_pfb_parity_all_shapes(N, M):
     e, r = err_fs(y, ref, h.sum()), err_rel(y, ref)
     log("  err_fs=%.3g err_rel=%.3g" % (e, r))
     assert e <= TOL_FS and r <= TOL_REL
+    check_pfb_elements(y, ref, h, N, M, iq)
 
 
 @pytest.mark.parametrize("N,M", [(64, 4), (1024, 8), (4096, 3)])
@@ -299,3 +301,4 @@ def test_pfb_production_full_size_sampled(monkeypatch):
     e, r = err_fs(y, ref, w.h.sum()), err_rel(y, ref)
     log("production sampled frames=%d err_fs=%.3g err_rel=%.3g" % (len(frames), e, r))
     assert e <= TOL_FS and r <= TOL_REL
+    check_pfb_elements(y, ref, w.h, w.N, w.M, iq, frames)
