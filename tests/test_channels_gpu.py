@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import siggen
-from gpu_util import err_fs, f32, log, need_gpu, run_pfb, to_dev
+from gpu_util import check_pfb_elements, err_fs, f32, log, need_gpu, run_pfb, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,7 @@ def test_chosen_channels_are_the_full_spectrum_columns(N, M):
     p.set_channels(ch)
     got = run_pfb(p, d, [n], torch)
     assert err_fs(got, ref, h.sum()) <= 1e-5
+    check_pfb_elements(got, ref, h, N, M, iq)
 
 
 def test_chosen_channels_across_buffers_and_switches():

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import siggen
-from gpu_util import err_fs, err_rel, f32, log, need_gpu, run_ddc, to_dev
+from gpu_util import check_ddc_elements, err_fs, err_rel, f32, log, need_gpu, run_ddc, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +79,7 @@ def test_chirp_parity(ntones, T, D, n):
     e, r = err_fs(y, ref, h.sum()), err_rel(y, ref)
     log("  err_fs=%.3g err_rel=%.3g" % (e, r))
     assert e <= TOL_FS and r <= tol_rel(T)
+    check_ddc_elements(y, ref, f32(h), D, iq)
     assert np.array_equal(dd.phase(), phases_after(inc, phi0, K, n))
 
 
@@ -213,7 +214,9 @@ def test_chirp_bank_full_size_sampled():
     ti = np.concatenate([rng.integers(0, 1000, len(outs)), rng.integers(0, 1000, 150)])
     oi = np.concatenate([outs, rng.integers(0, total, 150)])
     y = out.cpu().numpy()[ti, oi]
-    ref = oracle.ddc_points(inc, w.phase0, f32(w.h), w.D, ti, oi, iq=d.cpu().numpy(), chirp=K)
+    iq = d.cpu().numpy()
+    ref = oracle.ddc_points(inc, w.phase0, f32(w.h), w.D, ti, oi, iq=iq, chirp=K)
     e, r = err_fs(y, ref, w.h.sum()), err_rel(y, ref)
     log("  err_fs=%.3g err_rel=%.3g" % (e, r))
     assert e <= TOL_FS and r <= tol_rel(1024)
+    check_ddc_elements(y, ref, f32(w.h), w.D, iq, tones=ti, outs=oi)
