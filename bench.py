@@ -623,7 +623,7 @@ def bench_pcie(rf, torch, siggen, steps):
 def bench_large(rf, torch, siggen, steps, warmup):
     """N = 10^5 channels (Sec. III.A, Fig. 3), M = 8, Kaiser(9): 2^27 samples of
     the production stream in 2^24-sample buffers, through the fold pass and
-    the four-step FFT (N = 250 x 400)."""
+    the four-step FFT (N = 200 x 500)."""
     w = siggen.pfb_production()
     N, M = 100000, 8
     h = siggen.pfb_prototype(N, M, "kaiser", 9.0)
@@ -659,7 +659,7 @@ def bench_large(rf, torch, siggen, steps, warmup):
             "us_per_buffer": kern_s * 1e6,
             "hbm_gbs_44B_per_sample": 44.0 * buf / kern_s / 1e9,
             "config": {"workload": "pfb N=100000 M=8 kaiser9, 2^27 samples in 2^24-sample buffers, "
-                                   "fold + four-step FFT (250 x 400)", "N": N, "M": M}}
+                                   "fold + four-step FFT (200 x 500)", "N": N, "M": M}}
 
 
 # -------------------------------------------------------------------- Tx

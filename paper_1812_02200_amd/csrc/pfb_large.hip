@@ -316,12 +316,11 @@ __global__ void __launch_bounds__(kStepWG) large_fft_step(StepDesc d, int64_t N,
 static int split_radices(int L, int *rad)
 {
     int n = 0;
-    while (L % 8 == 0 && L > 8) { rad[n++] = 8; L /= 8; }
+    while (L % 8 == 0) { rad[n++] = 8; L /= 8; }
     while (L % 4 == 0) { rad[n++] = 4; L /= 4; }
     while (L % 2 == 0) { rad[n++] = 2; L /= 2; }
     while (L % 5 == 0) { rad[n++] = 5; L /= 5; }
     while (L % 3 == 0) { rad[n++] = 3; L /= 3; }
-    if (L == 8) rad[n++] = 8, L = 1;
     return L == 1 ? n : -1;
 }
 
@@ -342,11 +341,26 @@ bool large_plan(int64_t N, LargePlan *pl)
     if (N <= 4096) {
         n1 = N;
     } else {
-        // the most balanced split N1 * N2 (N1 <= N2 <= 4096): the column step,
-        // whose loads and stores are strided, gets the shorter transforms and
-        // so the most columns per work-group
-        for (int64_t d = 2; d * d <= N; ++d)
-            if (N % d == 0 && N / d <= 4096) n1 = d;
+        // N1 * N2 with N1 <= N2 <= 4096: the column step, whose loads and
+        // stores are strided, gets the shorter transforms and so the most
+        // columns per work-group.  Among the splits within a factor of two of
+        // the balanced one, the fewest Stockham passes in all (each pass is a
+        // round trip through LDS and a barrier), the most balanced on a tie;
+        // else the most balanced split.
+        int best = 1 << 30;
+        int tmp[16];
+        for (int64_t d = 2; d * d <= N; ++d) {
+            if (N % d || N / d > 4096) continue;
+            if (4 * d * d >= N) {
+                const int p1 = split_radices((int)d, tmp), p2 = split_radices((int)(N / d), tmp);
+                if (p1 > 0 && p2 > 0 && p1 + p2 <= best) {
+                    best = p1 + p2;
+                    n1 = d;
+                }
+            } else if (best == (1 << 30)) {
+                n1 = d;
+            }
+        }
         if (!n1) return false;
         n2 = N / n1;
     }

@@ -47,7 +47,7 @@ def _feed(p, d, sizes, static, torch):
 
 
 @pytest.mark.parametrize("N,M,first,second", [
-    (100000, 4, 100000 * 4 + 30 * 100000 + 17, 5 * 100000 + 3),   # two-step plan, 250 x 400
+    (100000, 4, 100000 * 4 + 30 * 100000 + 17, 5 * 100000 + 3),   # two-step plan, 200 x 500
     (3000, 3, 3000 * 3 + 600 * 3000 + 11, 40 * 3000 + 7),          # one-step plan
     (1024, 8, 1024 * 8 + 900 * 1024 + 5, 77 * 1024 + 1),           # fused kernel, no scratch
 ])
