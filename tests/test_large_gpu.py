@@ -87,7 +87,8 @@ def test_one_step_non_power_of_two_full(N, M):
     check(y, ref, h, ks, "one-step N=%d M=%d" % (N, M), iq)
 
 
-@pytest.mark.parametrize("N,M", [(8192, 4), (6000, 2), (9000, 4), (100000, 8), (65536, 2), (1 << 20, 1), (12000, 12)])
+@pytest.mark.parametrize("N,M", [(8192, 4), (6000, 2), (9000, 4), (100000, 8), (65536, 2), (1 << 20, 1), (12000, 12),
+                                 (1 << 24, 1)])
 def test_four_step(N, M):
     rf = _rf()
     import torch
